@@ -1,0 +1,178 @@
+/*
+ * miqr: MI355X-native Householder QR and least squares (C ABI).
+ *
+ * Method: "A 3D Parallel Algorithm for QR Decomposition" (Ballard, Demmel,
+ * Grigori, Jacquelin, Knight).  The factorisation is the Elmroth-Gustavson
+ * recursion QR-EG (Alg. 2): split the columns in two, factor the left half,
+ * update the right half with the compact-WY product C <- C - V (T^T (V^T C))
+ * (Sec. 2.3, eq. for the basis-kernel update), factor the lower right block,
+ * and assemble V and T (Sec. 2.3, basis-kernel assembly).  Below a column
+ * cutoff the base case is the TSQR panel factorisation of 1D-CAQR-EG (Sec. 5,
+ * Sec. 6.1, App. C): local QR of row blocks, a reduction tree over the stacked
+ * R factors, a downsweep that forms the leading columns of Q, and Householder
+ * reconstruction (App. C.2) of V, T and R.
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are column-major: element (i, j) of a matrix with leading
+ *    dimension ld is at p[i + j*ld].  Sizes and leading dimensions are int64_t.
+ *  - Matrix pointers are DEVICE pointers (HIP device memory of the handle's
+ *    device) unless a parameter says "host".  The caller owns every matrix it
+ *    passes; the library never frees or retains them past the call.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *    Every call is enqueued on that stream and returns without waiting,
+ *    unless a host-side output (qr_info) is requested, in which case the call
+ *    synchronises the stream before returning.
+ *  - Arguments are validated before anything is enqueued; on MIQR_EINVAL no
+ *    device memory is touched.
+ *  - A handle is not thread-safe; use one handle per host thread.  Calls on one
+ *    handle that overlap on different streams race on its workspace.
+ *
+ * Output representation (Sec. 2.3, "Householder representation"): after
+ * qr_factor, A's upper triangle holds R (n x n), its strict lower trapezoid
+ * holds V (unit lower trapezoidal, unit diagonal implicit), and T (n x n upper
+ * triangular) satisfies Q = I - V T V^T, A = Q R.  Reflector signs follow
+ * R_jj = -sign(alpha_j) * ||x_j|| (the sign that Householder reconstruction
+ * selects with S_jj = sgn(X_jj)), so the result matches unblocked Householder
+ * QR with the LAPACK dlarfg rule.
+ */
+#ifndef MIQR_H
+#define MIQR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum miqr_status {
+    MIQR_OK = 0,
+    MIQR_EINVAL = 1,    /* invalid argument; nothing was enqueued */
+    MIQR_ENOMEM = 2,    /* workspace allocation failed */
+    MIQR_EHIP = 3,      /* a HIP runtime or launch error */
+    MIQR_ESINGULAR = 4, /* lstsq: R has an exactly zero diagonal entry */
+    MIQR_ENOCONV = 5,   /* refinement did not reach its target; FP64 fallback used */
+    MIQR_EBUSY = 6,     /* server back-pressure: no slot or memory right now */
+    MIQR_ENOTSUP = 7    /* option combination not supported */
+} miqr_status;
+
+typedef enum miqr_precision {
+    MIQR_FP64 = 0,       /* every step in FP64 (FP64 MFMA for the updates) */
+    MIQR_MIXED_FP32 = 1, /* trailing-update GEMMs on FP32 MFMA, FP32 accumulate */
+    MIQR_MIXED_BF16 = 2  /* trailing-update GEMMs on BF16 MFMA, FP32 accumulate */
+} miqr_precision;
+
+typedef struct miqr_ctx *miqr_handle;
+
+/* Tuning and output options.  A NULL qr_opts* means all defaults.  Zero in a
+ * tuning field means "choose automatically". */
+typedef struct qr_opts {
+    int64_t b;         /* EG recursion cutoff: columns at or below b go to TSQR
+                          (Alg. 2 base case, n <= b).  Max 64. */
+    int64_t leaf_rows; /* TSQR leaf row-block height: 128 or 256 */
+    int64_t chain;     /* leaf blocks reduced in sequence by one workgroup */
+    int64_t arity;     /* TSQR tree arity above the leaf chains (>= 2) */
+    int32_t precision; /* miqr_precision */
+    int32_t normalize; /* nonzero: store R~ = D R with D = diag(sign(R_jj)) so
+                          that diag(R~) >= 0; then A = Q D R~ with
+                          Q = I - V T V^T.  sign_out must be given. */
+    double *sign_out;  /* device, n doubles: D (+1/-1), written when normalize */
+    double *Q;         /* device, optional m x n explicit thin Q (Q D when
+                          normalize) */
+    int64_t ldq;
+} qr_opts;
+
+/* Host-side result of qr_lstsq. */
+typedef struct qr_info {
+    int32_t iterations;     /* refinement iterations performed (0 for FP64) */
+    int32_t fallback;       /* 1 if the mixed form fell back to FP64 */
+    int32_t precision_used; /* miqr_precision of the factors finally used */
+    int32_t singular_index; /* 1-based index j with R_jj == 0, or 0 */
+    double backward_error;  /* max over right-hand sides of
+                               ||A^T r|| / (||A||_F (||A||_F ||x|| + ||r||)) */
+} qr_info;
+
+/* Create a handle bound to HIP device `device`; it owns a lazily grown device
+ * workspace.  Returns MIQR_EINVAL for a bad device index. */
+miqr_status miqr_create(miqr_handle *handle, int device);
+
+/* Release the handle and its workspace.  Pending work on streams that use the
+ * handle must have completed. */
+miqr_status miqr_destroy(miqr_handle handle);
+
+/* Static description of a status code. */
+const char *miqr_status_string(miqr_status status);
+
+/* Text of the last error recorded on the handle (empty if none). */
+const char *miqr_last_error(miqr_handle handle);
+
+/* Bytes of device workspace qr_factor needs for this shape (informational;
+ * the handle allocates it on first use). */
+int64_t qr_workspace_size(int64_t m, int64_t n, const qr_opts *opts);
+
+/* Flops (2 per multiply-add) of the GEMMs that the most recent qr_factor on
+ * this handle launched: the algorithmic count of the EG updates, reported
+ * beside the nominal 2mn^2 - 2n^3/3 (Alg. 2 forms the full T, which costs
+ * more than the nominal count). */
+double miqr_last_gemm_flops(miqr_handle handle);
+
+/* QR factorisation in place (Alg. 2 with the TSQR base case of Sec. 6.1).
+ *   A  (m x n, lda >= m, m >= n >= 1): on return R in the upper triangle and
+ *      V's strict lower trapezoid below it.
+ *   T  (n x n, ldt >= n): the full upper triangular kernel of Alg. 2's
+ *      assembly; its strict lower triangle is set to zero.
+ *   opts: see qr_opts; opts->Q (if set) receives the explicit thin Q.
+ * Errors: MIQR_EINVAL (m < n, n < 1, lda < m, ldt < n, NULL A or T, b out of
+ * range, normalize without sign_out, Q with ldq < m), MIQR_ENOMEM, MIQR_EHIP. */
+miqr_status qr_factor(miqr_handle handle, void *stream, int64_t m, int64_t n,
+                      double *A, int64_t lda, double *T, int64_t ldt,
+                      const qr_opts *opts);
+
+/* Apply the orthogonal factor from qr_factor (Sec. 2.3, Q = I - V T V^T):
+ *   trans 'N': C <- Q C;   trans 'T': C <- Q^T C.
+ *   VR (m x n, lda) and T (n x n, ldt) as returned by qr_factor; C is m x k
+ *   (ldc >= m), overwritten.  Evaluated right to left as three products
+ *   (V^T C, then T or T^T, then C - V (.)), the order the paper states for the
+ *   basis-kernel update.
+ * Errors: MIQR_EINVAL (bad trans, m < n, k < 0, ld too small, NULL pointers). */
+miqr_status qr_apply_q(miqr_handle handle, void *stream, char trans, int64_t m,
+                       int64_t n, int64_t k, const double *VR, int64_t lda,
+                       const double *T, int64_t ldt, double *C, int64_t ldc);
+
+/* Explicit thin Q = (I - V T V^T)[I_n; 0] (m x n, ldq >= m) from the factors.
+ * If sign (device, n doubles) is non-NULL the columns are scaled by it
+ * (Q D for factors computed with normalize). */
+miqr_status qr_form_q(miqr_handle handle, void *stream, int64_t m, int64_t n,
+                      const double *VR, int64_t lda, const double *T,
+                      int64_t ldt, const double *sign, double *Q, int64_t ldq);
+
+/* Least squares min ||B_j - A x_j||_2 for nrhs right-hand sides (the use that
+ * motivates QR in Sec. 1).  A (m x n, m >= n) is overwritten by its factors;
+ * B (m x nrhs, ldb >= m) by the solutions in rows 0..n-1 (LAPACK gels
+ * convention).  FP64: factor, c = Q^T b, back substitution R x = c[0:n].
+ * Mixed precisions: the factorisation runs with FP32/BF16 trailing updates and
+ * the solution is refined in FP64 against a device copy of the original A
+ * (R-preconditioned conjugate gradients on the normal equations, FP64
+ * residuals) until the backward error is <= 1e-13; if that fails the problem
+ * is refactored in FP64 (info->fallback = 1, status MIQR_ENOCONV).
+ *   info (host, may be NULL): when given, the call synchronises the stream and
+ *   fills it.
+ * Errors: MIQR_EINVAL, MIQR_ENOMEM, MIQR_EHIP, MIQR_ESINGULAR (some R_jj == 0
+ * exactly; B is left holding Q^T b), MIQR_ENOCONV. */
+miqr_status qr_lstsq(miqr_handle handle, void *stream, int64_t m, int64_t n,
+                     int64_t nrhs, double *A, int64_t lda, double *B,
+                     int64_t ldb, const qr_opts *opts, qr_info *info);
+
+/* Solve with the triangular factor: X <- R^{-1} X for the n x n upper triangle
+ * of VR (lda) and X (n x nrhs, ldx >= n).  Returns MIQR_ESINGULAR without
+ * touching X if some R_jj == 0 (checked on the device; the call then
+ * synchronises the stream). */
+miqr_status qr_solve_r(miqr_handle handle, void *stream, int64_t n,
+                       int64_t nrhs, const double *VR, int64_t lda, double *X,
+                       int64_t ldx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MIQR_H */

@@ -1,0 +1,218 @@
+"""Python binding of libmiqr (MI355X Householder QR / least squares, C ABI in
+include/miqr.h).  Argument marshalling only: every step runs in the HIP
+library; this module never computes a factorisation itself and raises if the
+library is missing.
+
+Matrices are float64 torch tensors on the GPU in column-major layout: a tensor
+``A`` of shape (m, n) with ``A.stride(0) == 1`` and ``A.stride(1) >= m`` (for
+example ``colmajor(m, n)`` or ``torch.empty(n, m).t()``).  Calls are enqueued on
+torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmiqr.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESINGULAR, ENOCONV, EBUSY, ENOTSUP = range(8)
+FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
+
+_i64 = ctypes.c_int64
+_vp = ctypes.c_void_p
+
+
+class MiqrError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("miqr status %d: %s" % (status, message))
+        self.status = status
+
+
+class QrOpts(ctypes.Structure):
+    _fields_ = [("b", _i64), ("leaf_rows", _i64), ("chain", _i64), ("arity", _i64),
+                ("precision", ctypes.c_int32), ("normalize", ctypes.c_int32),
+                ("sign_out", _vp), ("Q", _vp), ("ldq", _i64)]
+
+
+class QrInfo(ctypes.Structure):
+    _fields_ = [("iterations", ctypes.c_int32), ("fallback", ctypes.c_int32),
+                ("precision_used", ctypes.c_int32), ("singular_index", ctypes.c_int32),
+                ("backward_error", ctypes.c_double)]
+
+
+_lib = None
+
+
+def lib():
+    """Load libmiqr.so; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libmiqr.so is not built (run __graft_entry__.build() or "
+                              "python -m paper_1805_05278_amd.build)")
+        L = ctypes.CDLL(LIB_PATH)
+        st = ctypes.c_int
+        L.miqr_create.argtypes = [ctypes.POINTER(_vp), ctypes.c_int]
+        L.miqr_create.restype = st
+        L.miqr_destroy.argtypes = [_vp]
+        L.miqr_destroy.restype = st
+        L.miqr_status_string.argtypes = [st]
+        L.miqr_status_string.restype = ctypes.c_char_p
+        L.miqr_last_error.argtypes = [_vp]
+        L.miqr_last_error.restype = ctypes.c_char_p
+        L.qr_workspace_size.argtypes = [_i64, _i64, ctypes.POINTER(QrOpts)]
+        L.qr_workspace_size.restype = _i64
+        L.qr_factor.argtypes = [_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64,
+                                ctypes.POINTER(QrOpts)]
+        L.qr_factor.restype = st
+        L.qr_apply_q.argtypes = [_vp, _vp, ctypes.c_char, _i64, _i64, _i64, _vp, _i64, _vp,
+                                 _i64, _vp, _i64]
+        L.qr_apply_q.restype = st
+        L.qr_form_q.argtypes = [_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _vp, _i64]
+        L.qr_form_q.restype = st
+        L.qr_lstsq.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64,
+                               ctypes.POINTER(QrOpts), ctypes.POINTER(QrInfo)]
+        L.qr_lstsq.restype = st
+        L.qr_solve_r.argtypes = [_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64]
+        L.qr_solve_r.restype = st
+        L.miqr_last_gemm_flops.argtypes = [_vp]
+        L.miqr_last_gemm_flops.restype = ctypes.c_double
+        _lib = L
+    return _lib
+
+
+def _stream():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def colmajor(m: int, n: int, device="cuda", dtype=None):
+    """Uninitialised column-major (m, n) float64 tensor."""
+    import torch
+    dtype = dtype or torch.float64
+    return torch.empty((n, m), dtype=dtype, device=device).t()
+
+
+def to_colmajor(x, device="cuda"):
+    """Copy a 2-D array-like into a new column-major float64 GPU tensor."""
+    import torch
+    t = torch.as_tensor(x, dtype=torch.float64)
+    if t.dim() == 1:
+        t = t.reshape(-1, 1)
+    return t.t().contiguous().to(device).t()
+
+
+def _mat(x, name: str):
+    import torch
+    if not isinstance(x, torch.Tensor) or x.dtype != torch.float64 or not x.is_cuda:
+        raise TypeError("%s must be a float64 CUDA tensor" % name)
+    if x.dim() != 2:
+        raise ValueError("%s must be 2-D" % name)
+    if x.shape[0] > 1 and x.stride(0) != 1:
+        raise ValueError("%s must be column-major (stride(0) == 1)" % name)
+    ld = max(x.stride(1), x.shape[0], 1) if x.shape[1] > 1 else max(x.shape[0], 1)
+    return ctypes.c_void_p(x.data_ptr()), ld
+
+
+@dataclass
+class Info:
+    iterations: int
+    fallback: int
+    precision_used: int
+    singular_index: int
+    backward_error: float
+
+
+class Handle:
+    """Owns a miqr handle (device workspace) for one device."""
+
+    def __init__(self, device: int = 0):
+        self._h = _vp()
+        st = lib().miqr_create(ctypes.byref(self._h), device)
+        if st != OK:
+            raise MiqrError(st, lib().miqr_status_string(st).decode())
+
+    def close(self):
+        if self._h:
+            lib().miqr_destroy(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st: int):
+        if st != OK:
+            msg = lib().miqr_last_error(self._h).decode() or lib().miqr_status_string(st).decode()
+            raise MiqrError(st, msg)
+
+    @property
+    def last_gemm_flops(self) -> float:
+        return float(lib().miqr_last_gemm_flops(self._h))
+
+    @staticmethod
+    def opts(b=0, leaf_rows=0, chain=0, arity=0, precision=FP64, normalize=False,
+             sign_out=None, Q=None) -> QrOpts:
+        o = QrOpts()
+        o.b, o.leaf_rows, o.chain, o.arity = b, leaf_rows, chain, arity
+        o.precision = precision
+        o.normalize = 1 if normalize else 0
+        o.sign_out = sign_out.data_ptr() if sign_out is not None else None
+        if Q is not None:
+            qp, ldq = _mat(Q, "Q")
+            o.Q, o.ldq = qp.value, ldq
+        return o
+
+    def workspace_size(self, m: int, n: int, opts: Optional[QrOpts] = None) -> int:
+        return int(lib().qr_workspace_size(m, n, ctypes.byref(opts) if opts else None))
+
+    def factor(self, A, T, opts: Optional[QrOpts] = None):
+        """In-place QR of A (m x n); T (n x n) receives the kernel."""
+        ap, lda = _mat(A, "A")
+        tp, ldt = _mat(T, "T")
+        m, n = A.shape
+        self._check(lib().qr_factor(self._h, _stream(), m, n, ap, lda, tp, ldt,
+                                    ctypes.byref(opts) if opts else None))
+
+    def apply_q(self, trans: str, VR, T, C):
+        vp, lda = _mat(VR, "VR")
+        tp, ldt = _mat(T, "T")
+        cp, ldc = _mat(C, "C")
+        m, n = VR.shape
+        self._check(lib().qr_apply_q(self._h, _stream(), trans.encode(), m, n, C.shape[1],
+                                     vp, lda, tp, ldt, cp, ldc))
+
+    def form_q(self, VR, T, Q, sign=None):
+        vp, lda = _mat(VR, "VR")
+        tp, ldt = _mat(T, "T")
+        qp, ldq = _mat(Q, "Q")
+        m, n = VR.shape
+        sp = ctypes.c_void_p(sign.data_ptr()) if sign is not None else None
+        self._check(lib().qr_form_q(self._h, _stream(), m, n, vp, lda, tp, ldt, sp, qp, ldq))
+
+    def solve_r(self, VR, X):
+        vp, lda = _mat(VR, "VR")
+        xp, ldx = _mat(X, "X")
+        n = VR.shape[1]
+        self._check(lib().qr_solve_r(self._h, _stream(), n, X.shape[1], vp, lda, xp, ldx))
+
+    def lstsq(self, A, B, opts: Optional[QrOpts] = None, want_info: bool = True):
+        """Least squares in place: A <- factors, B[:n] <- solutions.  Returns
+        (status, Info or None); raises on errors other than ENOCONV/ESINGULAR."""
+        ap, lda = _mat(A, "A")
+        bp, ldb = _mat(B, "B")
+        m, n = A.shape
+        info = QrInfo()
+        st = lib().qr_lstsq(self._h, _stream(), m, n, B.shape[1], ap, lda, bp, ldb,
+                            ctypes.byref(opts) if opts else None,
+                            ctypes.byref(info) if want_info else None)
+        if st not in (OK, ENOCONV, ESINGULAR):
+            self._check(st)
+        out = Info(info.iterations, info.fallback, info.precision_used, info.singular_index,
+                   info.backward_error) if want_info else None
+        return st, out

@@ -1,0 +1,547 @@
+// C ABI of libmiqr: handle and workspace management, the Elmroth-Gustavson
+// recursion driver (Alg. 2), apply/form Q, triangular solve and least squares.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "common.h"
+#include "gemm.h"
+#include "miqr.h"
+#include "solve.h"
+#include "tsqr.h"
+
+using namespace miqr;
+
+struct miqr_ctx {
+  int device = 0;
+  char* ws = nullptr;
+  size_t ws_bytes = 0;
+  int* dflag = nullptr;
+  std::string err;
+  double gemm_flops = 0.0;  // multiply-add flops of the GEMMs launched by the last call
+};
+
+namespace {
+
+miqr_status fail(miqr_handle h, miqr_status st, const std::string& msg) {
+  if (h) h->err = msg;
+  return st;
+}
+
+miqr_status hip_fail(miqr_handle h, hipError_t e, const char* where) {
+  return fail(h, MIQR_EHIP, std::string(where) + ": " + hipGetErrorString(e));
+}
+
+miqr_status ensure_ws(miqr_handle h, size_t bytes) {
+  if (bytes <= h->ws_bytes) return MIQR_OK;
+  hipError_t e = hipSetDevice(h->device);
+  if (e != hipSuccess) return hip_fail(h, e, "hipSetDevice");
+  if (h->ws) {
+    e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(h, e, "hipDeviceSynchronize");
+    hipFree(h->ws);
+    h->ws = nullptr;
+    h->ws_bytes = 0;
+  }
+  size_t want = std::max<size_t>(bytes, (size_t)64 << 20);
+  e = hipMalloc((void**)&h->ws, want);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    h->ws = nullptr;
+    return fail(h, MIQR_ENOMEM, "workspace allocation of " + std::to_string(want) + " bytes failed");
+  }
+  h->ws_bytes = want;
+  return MIQR_OK;
+}
+
+// Bump allocator over the handle's workspace (doubles, 256-byte aligned).
+struct Arena {
+  double* base;
+  int64_t off = 0;
+  double* take(int64_t n) {
+    double* p = base ? base + off : nullptr;
+    off += (n + 31) & ~int64_t(31);
+    return p;
+  }
+};
+
+struct Tuning {
+  int64_t b = 64;
+  int leaf_rows = 0;
+  int chain = 0;
+  int arity = 2;
+};
+
+Tuning tuning_from(const qr_opts* o, int64_t m, int64_t n) {
+  Tuning t;
+  if (o) {
+    if (o->b > 0) t.b = o->b;
+    if (o->leaf_rows > 0) t.leaf_rows = (int)o->leaf_rows;
+    if (o->chain > 0) t.chain = (int)o->chain;
+    if (o->arity >= 2) t.arity = (int)o->arity;
+  }
+  t.b = std::min<int64_t>(t.b, std::min<int64_t>(n, kNB));
+  (void)m;
+  return t;
+}
+
+int64_t split_point(int64_t nk, int64_t b) {
+  // Alg. 2 splits at floor(n/2); any split gives the same factors in exact
+  // arithmetic.  Rounding the left width up to a multiple of the cutoff keeps
+  // every panel full width and the GEMM operands aligned.
+  int64_t n1 = ((nk / 2 + b - 1) / b) * b;
+  if (n1 >= nk) n1 = nk / 2;
+  return std::max<int64_t>(n1, 1);
+}
+
+// Largest TSQR workspace over the panels the recursion will visit.
+void max_panel_ws(int64_t mk, int64_t nk, const Tuning& t, int64_t* best) {
+  if (nk <= t.b) {
+    TsqrPlan p = tsqr_plan(mk, (int)nk, t.leaf_rows, t.chain, t.arity, nullptr);
+    *best = std::max(*best, p.workspace_doubles);
+    return;
+  }
+  const int64_t n1 = split_point(nk, t.b);
+  max_panel_ws(mk, n1, t, best);
+  max_panel_ws(mk - n1, nk - n1, t, best);
+}
+
+struct FactorLayout {
+  int64_t tsqr = 0, wa = 0, wb = 0, scratch = 0, total = 0;
+};
+
+FactorLayout factor_layout(int64_t m, int64_t n, const Tuning& t) {
+  FactorLayout L;
+  max_panel_ws(m, n, t, &L.tsqr);
+  const int64_t n1 = (n > t.b) ? split_point(n, t.b) : 0;
+  const int64_t n2 = n - n1;
+  L.wa = std::max<int64_t>(n1 * n2, 1);
+  L.wb = L.wa;
+  L.scratch = std::max<int64_t>(int64_t(4) << 20, 4 * L.wa);
+  L.total = L.tsqr + L.wa + L.wb + L.scratch + 4 * 32;
+  return L;
+}
+
+struct EgCtx {
+  hipStream_t s;
+  double* A;
+  int64_t lda;
+  double* T;
+  int64_t ldt;
+  Tuning tune;
+  double* tsqr_ws;
+  double* Wa;
+  double* Wb;
+  double* scratch;
+  int64_t scratch_n;
+  int update_compute;
+  double flops = 0.0;
+  hipError_t err = hipSuccess;
+  // thin Q for a single-panel factorisation
+  double* Q = nullptr;
+  int64_t ldq = 0;
+  int normalize = 0;
+  double* sign = nullptr;
+};
+
+void run_gemm(EgCtx& e, const GemmDesc& d) {
+  if (e.err != hipSuccess) return;
+  e.err = gemm(d, e.s, e.scratch, e.scratch_n, &e.flops);
+}
+
+// Alg. 2 (QR-EG) on the sub-problem with top-left corner (r0, c0), mk rows
+// (to the bottom of A) and nk columns.
+void eg(EgCtx& e, int64_t r0, int64_t c0, int64_t mk, int64_t nk) {
+  if (e.err != hipSuccess) return;
+  double* A = e.A;
+  const int64_t lda = e.lda, ldt = e.ldt;
+  if (nk <= e.tune.b) {
+    TsqrPlan p = tsqr_plan(mk, (int)nk, e.tune.leaf_rows, e.tune.chain, e.tune.arity, e.tsqr_ws);
+    e.err = tsqr_factor(p, e.s, A + r0 + c0 * lda, lda, e.T + c0 + c0 * ldt, ldt, e.Q, e.ldq,
+                        e.normalize, e.sign);
+    return;
+  }
+  const int64_t n1 = split_point(nk, e.tune.b), n2 = nk - n1;
+  eg(e, r0, c0, mk, n1);
+  double* VL = A + r0 + c0 * lda;
+  double* C = A + r0 + (c0 + n1) * lda;
+  double* TL = e.T + c0 + c0 * ldt;
+  GemmDesc d;
+  // M1 = V_L^T C
+  d = GemmDesc();
+  d.ta = 'T'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = mk;
+  d.A = VL; d.lda = lda; d.maskA = MASK_UNIT_LOWER;
+  d.B = C; d.ldb = lda; d.C = e.Wa; d.ldc = n1; d.compute = e.update_compute;
+  run_gemm(e, d);
+  // M2 = T_L^T M1
+  d = GemmDesc();
+  d.ta = 'T'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = n1;
+  d.A = TL; d.lda = ldt; d.maskA = MASK_UPPER;
+  d.B = e.Wa; d.ldb = n1; d.C = e.Wb; d.ldc = n1;
+  run_gemm(e, d);
+  // [B12; B22] = C - V_L M2
+  d = GemmDesc();
+  d.ta = 'N'; d.tb = 'N'; d.M = mk; d.N = n2; d.K = n1; d.alpha = -1.0; d.beta = 1.0;
+  d.A = VL; d.lda = lda; d.maskA = MASK_UNIT_LOWER;
+  d.B = e.Wb; d.ldb = n1; d.C = C; d.ldc = lda; d.compute = e.update_compute;
+  run_gemm(e, d);
+  eg(e, r0 + n1, c0 + n1, mk - n1, n2);
+  double* VR = A + (r0 + n1) + (c0 + n1) * lda;
+  double* TR = e.T + (c0 + n1) + (c0 + n1) * ldt;
+  // M3 = V_L^T [0; V_R] = V_L[n1:, :]^T V_R
+  d = GemmDesc();
+  d.ta = 'T'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = mk - n1;
+  d.A = A + (r0 + n1) + c0 * lda; d.lda = lda;
+  d.B = VR; d.ldb = lda; d.maskB = MASK_UNIT_LOWER; d.C = e.Wa; d.ldc = n1;
+  run_gemm(e, d);
+  // M4 = M3 T_R
+  d = GemmDesc();
+  d.ta = 'N'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = n2;
+  d.A = e.Wa; d.lda = n1; d.B = TR; d.ldb = ldt; d.maskB = MASK_UPPER;
+  d.C = e.Wb; d.ldc = n1;
+  run_gemm(e, d);
+  // T12 = -T_L M4
+  d = GemmDesc();
+  d.ta = 'N'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = n1; d.alpha = -1.0;
+  d.A = TL; d.lda = ldt; d.maskA = MASK_UPPER; d.B = e.Wb; d.ldb = n1;
+  d.C = e.T + c0 + (c0 + n1) * ldt; d.ldc = ldt;
+  run_gemm(e, d);
+}
+
+bool bad_ptr(const void* p) { return p == nullptr; }
+
+miqr_status do_factor(miqr_handle h, hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda,
+                      double* T, int64_t ldt, const qr_opts* o, int update_compute) {
+  const Tuning tune = tuning_from(o, m, n);
+  FactorLayout L = factor_layout(m, n, tune);
+  miqr_status st = ensure_ws(h, (size_t)L.total * sizeof(double));
+  if (st != MIQR_OK) return st;
+  Arena ar{(double*)h->ws};
+  EgCtx e;
+  e.s = s;
+  e.A = A;
+  e.lda = lda;
+  e.T = T;
+  e.ldt = ldt;
+  e.tune = tune;
+  e.tsqr_ws = ar.take(L.tsqr);
+  e.Wa = ar.take(L.wa);
+  e.Wb = ar.take(L.wb);
+  e.scratch = ar.take(L.scratch);
+  e.scratch_n = L.scratch;
+  e.update_compute = update_compute;
+  // A single TSQR panel can emit Q and the normalised R itself, except for
+  // square matrices whose last reflector is switched afterwards.
+  const bool single = n <= tune.b && m > n;
+  const int normalize = o ? o->normalize : 0;
+  double* sign = o ? o->sign_out : nullptr;
+  double* Q = o ? o->Q : nullptr;
+  const int64_t ldq = o ? o->ldq : 0;
+  zero_strict_lower(s, n, T, ldt);
+  if (single) {
+    e.Q = Q;
+    e.ldq = ldq;
+    e.normalize = normalize;
+    e.sign = sign;
+  }
+  eg(e, 0, 0, m, n);
+  if (e.err != hipSuccess) return hip_fail(h, e.err, "qr_factor");
+  if (m == n) square_last_column(s, n, A, lda, T, ldt);
+  if (!single) {
+    if (normalize) normalize_r(s, n, A, lda, sign);
+    if (Q) {
+      miqr_status st2 = qr_form_q(h, s, m, n, A, lda, T, ldt, normalize ? sign : nullptr, Q, ldq);
+      if (st2 != MIQR_OK) return st2;
+    }
+  }
+  h->gemm_flops = e.flops;
+  hipError_t le = hipGetLastError();
+  if (le != hipSuccess) return hip_fail(h, le, "qr_factor launch");
+  return MIQR_OK;
+}
+
+// C <- Q C or Q^T C with Q = I - V T V^T (three products, right to left).
+miqr_status do_apply(miqr_handle h, hipStream_t s, char trans, int64_t m, int64_t n, int64_t k,
+                     const double* VR, int64_t lda, const double* T, int64_t ldt, double* C,
+                     int64_t ldc, double* W1, double* W2, double* scratch, int64_t scratch_n) {
+  if (k == 0) return MIQR_OK;
+  GemmDesc d;
+  d.ta = 'T'; d.tb = 'N'; d.M = n; d.N = k; d.K = m;
+  d.A = VR; d.lda = lda; d.maskA = MASK_UNIT_LOWER; d.B = C; d.ldb = ldc; d.C = W1; d.ldc = n;
+  hipError_t e = gemm(d, s, scratch, scratch_n);
+  if (e == hipSuccess) {
+    d = GemmDesc();
+    d.ta = (trans == 'T') ? 'T' : 'N'; d.tb = 'N'; d.M = n; d.N = k; d.K = n;
+    d.A = T; d.lda = ldt; d.maskA = MASK_UPPER; d.B = W1; d.ldb = n; d.C = W2; d.ldc = n;
+    e = gemm(d, s, scratch, scratch_n);
+  }
+  if (e == hipSuccess) {
+    d = GemmDesc();
+    d.ta = 'N'; d.tb = 'N'; d.M = m; d.N = k; d.K = n; d.alpha = -1.0; d.beta = 1.0;
+    d.A = VR; d.lda = lda; d.maskA = MASK_UNIT_LOWER; d.B = W2; d.ldb = n; d.C = C; d.ldc = ldc;
+    e = gemm(d, s, scratch, scratch_n);
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "apply_q");
+  return MIQR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+miqr_status miqr_create(miqr_handle* handle, int device) {
+  if (!handle) return MIQR_EINVAL;
+  *handle = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess) {
+    (void)hipGetLastError();
+    return MIQR_EHIP;
+  }
+  if (device < 0 || device >= count) return MIQR_EINVAL;
+  miqr_ctx* c = new miqr_ctx();
+  c->device = device;
+  if (hipSetDevice(device) != hipSuccess || hipMalloc((void**)&c->dflag, 256) != hipSuccess) {
+    delete c;
+    return MIQR_EHIP;
+  }
+  *handle = c;
+  return MIQR_OK;
+}
+
+miqr_status miqr_destroy(miqr_handle h) {
+  if (!h) return MIQR_EINVAL;
+  hipSetDevice(h->device);
+  hipDeviceSynchronize();
+  if (h->ws) hipFree(h->ws);
+  if (h->dflag) hipFree(h->dflag);
+  delete h;
+  return MIQR_OK;
+}
+
+const char* miqr_status_string(miqr_status s) {
+  switch (s) {
+    case MIQR_OK: return "success";
+    case MIQR_EINVAL: return "invalid argument";
+    case MIQR_ENOMEM: return "out of device memory";
+    case MIQR_EHIP: return "HIP runtime error";
+    case MIQR_ESINGULAR: return "R has an exactly zero diagonal entry";
+    case MIQR_ENOCONV: return "iterative refinement did not converge (FP64 fallback used)";
+    case MIQR_EBUSY: return "busy (no slot or memory available)";
+    case MIQR_ENOTSUP: return "option combination not supported";
+  }
+  return "unknown status";
+}
+
+const char* miqr_last_error(miqr_handle h) { return h ? h->err.c_str() : ""; }
+
+int64_t qr_workspace_size(int64_t m, int64_t n, const qr_opts* o) {
+  if (m < n || n < 1) return 0;
+  return factor_layout(m, n, tuning_from(o, m, n)).total * (int64_t)sizeof(double);
+}
+
+double miqr_last_gemm_flops(miqr_handle h) { return h ? h->gemm_flops : 0.0; }
+
+miqr_status qr_factor(miqr_handle h, void* stream, int64_t m, int64_t n, double* A, int64_t lda,
+                      double* T, int64_t ldt, const qr_opts* o) {
+  if (!h) return MIQR_EINVAL;
+  h->err.clear();
+  if (n < 1 || m < n) return fail(h, MIQR_EINVAL, "need m >= n >= 1");
+  if (lda < m || ldt < n) return fail(h, MIQR_EINVAL, "leading dimension too small");
+  if (bad_ptr(A) || bad_ptr(T)) return fail(h, MIQR_EINVAL, "null matrix pointer");
+  int prec = o ? o->precision : MIQR_FP64;
+  if (prec != MIQR_FP64 && prec != MIQR_MIXED_FP32 && prec != MIQR_MIXED_BF16)
+    return fail(h, MIQR_EINVAL, "bad precision");
+  if (o && (o->b < 0 || o->b > kNB)) return fail(h, MIQR_EINVAL, "b must be in [0, 64]");
+  if (o && o->leaf_rows != 0 && o->leaf_rows != 128 && o->leaf_rows != 256)
+    return fail(h, MIQR_EINVAL, "leaf_rows must be 0, 128 or 256");
+  if (o && (o->chain < 0 || o->arity < 0 || o->arity == 1))
+    return fail(h, MIQR_EINVAL, "chain must be >= 0 and arity 0 or >= 2");
+  if (o && o->normalize && !o->sign_out) return fail(h, MIQR_EINVAL, "normalize needs sign_out");
+  if (o && o->Q && o->ldq < m) return fail(h, MIQR_EINVAL, "ldq < m");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
+  const int comp = prec == MIQR_MIXED_FP32 ? COMPUTE_F32
+                   : prec == MIQR_MIXED_BF16 ? COMPUTE_BF16 : COMPUTE_F64;
+  return do_factor(h, (hipStream_t)stream, m, n, A, lda, T, ldt, o, comp);
+}
+
+miqr_status qr_apply_q(miqr_handle h, void* stream, char trans, int64_t m, int64_t n, int64_t k,
+                       const double* VR, int64_t lda, const double* T, int64_t ldt, double* C,
+                       int64_t ldc) {
+  if (!h) return MIQR_EINVAL;
+  h->err.clear();
+  if (trans != 'N' && trans != 'T') return fail(h, MIQR_EINVAL, "trans must be 'N' or 'T'");
+  if (n < 1 || m < n || k < 0) return fail(h, MIQR_EINVAL, "need m >= n >= 1, k >= 0");
+  if (lda < m || ldt < n || ldc < m) return fail(h, MIQR_EINVAL, "leading dimension too small");
+  if (bad_ptr(VR) || bad_ptr(T) || bad_ptr(C)) return fail(h, MIQR_EINVAL, "null pointer");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
+  const int64_t scratch_n = std::max<int64_t>(int64_t(4) << 20, 4 * n * k);
+  miqr_status st = ensure_ws(h, (size_t)(2 * n * k + scratch_n + 128) * sizeof(double));
+  if (st != MIQR_OK) return st;
+  Arena ar{(double*)h->ws};
+  double* W1 = ar.take(n * k);
+  double* W2 = ar.take(n * k);
+  double* sc = ar.take(scratch_n);
+  return do_apply(h, (hipStream_t)stream, trans, m, n, k, VR, lda, T, ldt, C, ldc, W1, W2, sc,
+                  scratch_n);
+}
+
+miqr_status qr_form_q(miqr_handle h, void* stream, int64_t m, int64_t n, const double* VR,
+                      int64_t lda, const double* T, int64_t ldt, const double* sign, double* Q,
+                      int64_t ldq) {
+  if (!h) return MIQR_EINVAL;
+  if (n < 1 || m < n) return fail(h, MIQR_EINVAL, "need m >= n >= 1");
+  if (lda < m || ldt < n || ldq < m) return fail(h, MIQR_EINVAL, "leading dimension too small");
+  if (bad_ptr(VR) || bad_ptr(T) || bad_ptr(Q)) return fail(h, MIQR_EINVAL, "null pointer");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  // Q = [I; 0] - V (T V_top^T), V_top the unit lower n x n top of V.
+  const int64_t scratch_n = std::max<int64_t>(int64_t(4) << 20, 2 * n * n);
+  // The workspace may already be in use by a qr_factor on this stream; place W
+  // after the factorisation's region by sizing for both.
+  const size_t need = (size_t)(n * n + scratch_n + 64) * sizeof(double);
+  if (need > h->ws_bytes) {
+    miqr_status st = ensure_ws(h, need);
+    if (st != MIQR_OK) return st;
+  }
+  Arena ar{(double*)h->ws};
+  double* W = ar.take(n * n);
+  double* sc = ar.take(scratch_n);
+  GemmDesc d;
+  d.ta = 'N'; d.tb = 'T'; d.M = n; d.N = n; d.K = n;
+  d.A = T; d.lda = ldt; d.maskA = MASK_UPPER; d.B = VR; d.ldb = lda; d.maskB = MASK_UNIT_LOWER;
+  d.C = W; d.ldc = n;
+  hipError_t e = gemm(d, s, sc, scratch_n);
+  set_identity(s, m, n, Q, ldq);
+  if (e == hipSuccess) {
+    d = GemmDesc();
+    d.ta = 'N'; d.tb = 'N'; d.M = m; d.N = n; d.K = n; d.alpha = -1.0; d.beta = 1.0;
+    d.A = VR; d.lda = lda; d.maskA = MASK_UNIT_LOWER; d.B = W; d.ldb = n; d.C = Q; d.ldc = ldq;
+    e = gemm(d, s, sc, scratch_n);
+  }
+  if (e == hipSuccess && sign) scale_columns(s, m, n, Q, ldq, sign);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "qr_form_q");
+  return MIQR_OK;
+}
+
+miqr_status qr_solve_r(miqr_handle h, void* stream, int64_t n, int64_t nrhs, const double* VR,
+                       int64_t lda, double* X, int64_t ldx) {
+  if (!h) return MIQR_EINVAL;
+  if (n < 1 || nrhs < 0 || lda < n || ldx < n) return fail(h, MIQR_EINVAL, "bad sizes");
+  if (bad_ptr(VR) || bad_ptr(X)) return fail(h, MIQR_EINVAL, "null pointer");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  find_zero_diagonal(s, n, VR, lda, h->dflag);
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_solve_r");
+  if (flag) return fail(h, MIQR_ESINGULAR, "R(" + std::to_string(flag - 1) + ") == 0");
+  if (nrhs == 0) return MIQR_OK;
+  const int64_t scratch_n = int64_t(4) << 20;
+  miqr_status st = ensure_ws(h, (size_t)(scratch_n + 64) * sizeof(double));
+  if (st != MIQR_OK) return st;
+  e = solve_upper(s, n, nrhs, VR, lda, X, ldx, (double*)h->ws, scratch_n);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_solve_r");
+  return MIQR_OK;
+}
+
+miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t nrhs, double* A,
+                     int64_t lda, double* B, int64_t ldb, const qr_opts* o, qr_info* info) {
+  if (!h) return MIQR_EINVAL;
+  h->err.clear();
+  if (n < 1 || m < n || nrhs < 1) return fail(h, MIQR_EINVAL, "need m >= n >= 1, nrhs >= 1");
+  if (lda < m || ldb < m) return fail(h, MIQR_EINVAL, "leading dimension too small");
+  if (bad_ptr(A) || bad_ptr(B)) return fail(h, MIQR_EINVAL, "null pointer");
+  const int prec = o ? o->precision : MIQR_FP64;
+  if (prec != MIQR_FP64 && prec != MIQR_MIXED_FP32 && prec != MIQR_MIXED_BF16)
+    return fail(h, MIQR_EINVAL, "bad precision");
+  if (o && (o->b < 0 || o->b > kNB)) return fail(h, MIQR_EINVAL, "b must be in [0, 64]");
+  if (o && (o->normalize || o->Q)) return fail(h, MIQR_ENOTSUP, "lstsq takes no Q/normalize");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (prec != MIQR_FP64) return fail(h, MIQR_ENOTSUP, "mixed precision lstsq not built yet");
+
+  // Layout: factorisation workspace first, then T, W1, W2, and (for info) copies.
+  const Tuning tune = tuning_from(o, m, n);
+  FactorLayout L = factor_layout(m, n, tune);
+  const int64_t extra = n * n + 2 * n * nrhs + (info ? (m * n + m * nrhs + 3 * nrhs + n + 64) : 0) + 256;
+  miqr_status st = ensure_ws(h, (size_t)(L.total + extra) * sizeof(double));
+  if (st != MIQR_OK) return st;
+  Arena ar{(double*)h->ws};
+  ar.take(L.total);
+  double* T = ar.take(n * n);
+  double* W1 = ar.take(n * nrhs);
+  double* W2 = ar.take(n * nrhs);
+  double *A0 = nullptr, *B0 = nullptr, *nrm = nullptr;
+  if (info) {
+    A0 = ar.take(m * n);
+    B0 = ar.take(m * nrhs);
+    nrm = ar.take(3 * nrhs + n + 8);
+    copy_matrix(s, m, n, A, lda, A0, m);
+    copy_matrix(s, m, nrhs, B, ldb, B0, m);
+  }
+  // The factorisation uses the front of the workspace (do_factor re-derives
+  // the same layout, so the regions above stay untouched).
+  st = do_factor(h, s, m, n, A, lda, T, n, o, COMPUTE_F64);
+  if (st != MIQR_OK) return st;
+  // The factorisation's split-K scratch (same arena layout as do_factor) is free now.
+  Arena far{(double*)h->ws};
+  far.take(L.tsqr);
+  far.take(L.wa);
+  far.take(L.wb);
+  double* sc = far.take(L.scratch);
+  st = do_apply(h, s, 'T', m, n, nrhs, A, lda, T, n, B, ldb, W1, W2, sc, L.scratch);
+  if (st != MIQR_OK) return st;
+  find_zero_diagonal(s, n, A, lda, h->dflag);
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq");
+  if (flag) {
+    if (info) info->singular_index = flag;
+    return fail(h, MIQR_ESINGULAR, "R(" + std::to_string(flag - 1) + ") == 0");
+  }
+  e = solve_upper(s, n, nrhs, A, lda, B, ldb, sc, L.scratch);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq solve");
+  if (info) {
+    info->precision_used = MIQR_FP64;
+    // r = b - A x (into B0), g = A^T r (into W1), norms.
+    GemmDesc d;
+    d.ta = 'N'; d.tb = 'N'; d.M = m; d.N = nrhs; d.K = n; d.alpha = -1.0; d.beta = 1.0;
+    d.A = A0; d.lda = m; d.B = B; d.ldb = ldb; d.C = B0; d.ldc = m;
+    e = gemm(d, s, sc, L.scratch);
+    d = GemmDesc();
+    d.ta = 'T'; d.tb = 'N'; d.M = n; d.N = nrhs; d.K = m;
+    d.A = A0; d.lda = m; d.B = B0; d.ldb = m; d.C = W1; d.ldc = n;
+    if (e == hipSuccess) e = gemm(d, s, sc, L.scratch);
+    if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq residual");
+    column_sumsq(s, m, nrhs, B0, m, nrm);              // ||r||^2
+    column_sumsq(s, n, nrhs, W1, n, nrm + nrhs);       // ||A^T r||^2
+    column_sumsq(s, n, nrhs, B, ldb, nrm + 2 * nrhs);  // ||x||^2
+    column_sumsq(s, m, n, A0, m, nrm + 3 * nrhs);      // column norms of A
+    std::vector<double> hn(3 * nrhs + n);
+    e = hipMemcpyAsync(hn.data(), nrm, sizeof(double) * hn.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq info");
+    double fa = 0.0;
+    for (int64_t j = 0; j < n; ++j) fa += hn[3 * nrhs + j];
+    fa = std::sqrt(fa);
+    double worst = 0.0;
+    for (int64_t c = 0; c < nrhs; ++c) {
+      const double rn = std::sqrt(hn[c]), gn = std::sqrt(hn[nrhs + c]), xn = std::sqrt(hn[2 * nrhs + c]);
+      const double den = fa * (fa * xn + rn);
+      worst = std::max(worst, den > 0 ? gn / den : 0.0);
+    }
+    info->backward_error = worst;
+  }
+  return MIQR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,253 @@
+// MFMA GEMMs for gfx950: the six products of each EG recursion node (Alg. 2:
+// M1 = V_L^T C, M2 = T_L^T M1, C -= V_L M2, M3 = V_L^T [0; V_R], M4 = M3 T_R,
+// T12 = -T_L M4) and the compact-WY application of Q.
+//
+// One workgroup (4 waves, 2 x 2) computes a BM x BN tile of C; each wave a
+// (BM/2) x (BN/2) block of 16 x 16 MFMA tiles.  Operands are staged through
+// LDS in BK = 16 deep slices, k-major, with the next slice prefetched into
+// registers while the current one is multiplied.  The MFMA computes C^T tiles
+// (A' = op(B)^T, B' = op(A)^T) so that the lane-fast output index runs down a
+// column of the column-major C and stores coalesce.
+//
+// Structure masks turn the stored unit lower trapezoidal V (R above its
+// diagonal) and the upper triangular T into their mathematical values while
+// they are loaded, so the factors never have to be copied out of A.
+//
+// Split-K (the paper's 1DMM with the K dimension distributed, Sec. 4 and
+// Sec. 6.2) is used when the output has few tiles: each slice of K writes a
+// partial product and a second kernel adds the partials in a fixed order, so
+// results are bitwise reproducible.
+#include <algorithm>
+
+#include "common.h"
+#include "gemm.h"
+
+namespace miqr {
+
+struct GemmArgs {
+  int64_t M, N, K, kchunk;
+  double alpha, beta;
+  const double* A;
+  int64_t lda;
+  const double* B;
+  int64_t ldb;
+  double* C;
+  int64_t ldc;
+  double* P;  // split-K partials (M x N each) or null
+  int maskA, maskB;
+};
+
+template <int CMP>
+struct MfmaTraits;
+
+template <>
+struct MfmaTraits<COMPUTE_F64> {
+  typedef double T;
+  typedef d4 Acc;
+  static __device__ __forceinline__ Acc mma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+
+template <>
+struct MfmaTraits<COMPUTE_F32> {
+  typedef float T;
+  typedef f4 Acc;
+  static __device__ __forceinline__ Acc mma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+
+__device__ __forceinline__ double apply_mask(double v, int64_t r, int64_t c, int mask) {
+  if (mask == MASK_UNIT_LOWER) return (r < c) ? 0.0 : ((r == c) ? 1.0 : v);
+  if (mask == MASK_UPPER) return (r > c) ? 0.0 : v;
+  return v;
+}
+
+template <int BM, int BN, bool TA, bool TB, int CMP>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  typedef MfmaTraits<CMP> Tr;
+  typedef typename Tr::T T;
+  typedef typename Tr::Acc Acc;
+  constexpr int BK = 16;
+  constexpr int PAD = 1;
+  constexpr int WM = BM / 2, WN = BN / 2, SA = WM / 16, SB = WN / 16;
+  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
+  __shared__ T As[BK][BM + PAD];
+  __shared__ T Bs[BK][BN + PAD];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
+  const int wm = w & 1, wn = w >> 1;
+  const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t kend = min(g.K, kbeg + g.kchunk);
+
+  Acc acc[SA][SB];
+#pragma unroll
+  for (int a = 0; a < SA; ++a)
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
+
+  double ra[LA], rb[LB];
+  auto loadA = [&](int64_t k0) {
+#pragma unroll
+    for (int s = 0; s < LA; ++s) {
+      const int idx = t + 256 * s;
+      const int i = TA ? idx / BK : idx % BM;
+      const int k = TA ? idx % BK : idx / BM;
+      const int64_t gi = i0 + i, gk = k0 + k;
+      double v = 0.0;
+      if (gi < g.M && gk < kend) {
+        const int64_t r = TA ? gk : gi, c = TA ? gi : gk;
+        v = apply_mask(g.A[r + c * g.lda], r, c, g.maskA);
+      }
+      ra[s] = v;
+    }
+  };
+  auto loadB = [&](int64_t k0) {
+#pragma unroll
+    for (int s = 0; s < LB; ++s) {
+      const int idx = t + 256 * s;
+      const int j = TB ? idx % BN : idx / BK;
+      const int k = TB ? idx / BN : idx % BK;
+      const int64_t gj = j0 + j, gk = k0 + k;
+      double v = 0.0;
+      if (gj < g.N && gk < kend) {
+        const int64_t r = TB ? gj : gk, c = TB ? gk : gj;
+        v = apply_mask(g.B[r + c * g.ldb], r, c, g.maskB);
+      }
+      rb[s] = v;
+    }
+  };
+
+  if (kbeg < kend) {
+    loadA(kbeg);
+    loadB(kbeg);
+  }
+  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
+#pragma unroll
+    for (int s = 0; s < LA; ++s) {
+      const int idx = t + 256 * s;
+      const int i = TA ? idx / BK : idx % BM;
+      const int k = TA ? idx % BK : idx / BM;
+      As[k][i] = (T)ra[s];
+    }
+#pragma unroll
+    for (int s = 0; s < LB; ++s) {
+      const int idx = t + 256 * s;
+      const int j = TB ? idx % BN : idx / BK;
+      const int k = TB ? idx / BN : idx % BK;
+      Bs[k][j] = (T)rb[s];
+    }
+    __syncthreads();
+    if (k0 + BK < kend) {
+      loadA(k0 + BK);
+      loadB(k0 + BK);
+    }
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      T af[SA], bf[SB];
+#pragma unroll
+      for (int a = 0; a < SA; ++a) af[a] = As[4 * ks + lk][wm * WM + 16 * a + li];
+#pragma unroll
+      for (int b = 0; b < SB; ++b) bf[b] = Bs[4 * ks + lk][wn * WN + 16 * b + li];
+#pragma unroll
+      for (int a = 0; a < SA; ++a)
+#pragma unroll
+        for (int b = 0; b < SB; ++b) acc[a][b] = Tr::mma(bf[b], af[a], acc[a][b]);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < SA; ++a) {
+    const int64_t i = i0 + wm * WM + 16 * a + li;
+    if (i >= g.M) continue;
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
+        if (j >= g.N) continue;
+        const double v = g.alpha * (double)acc[a][b][r];
+        if (g.P) {
+          g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = v;
+        } else {
+          double* cp = g.C + i + j * g.ldc;
+          *cp = (g.beta == 0.0) ? v : v + g.beta * *cp;
+        }
+      }
+  }
+}
+
+__global__ void k_splitk_reduce(const double* P, int nsplit, int64_t M, int64_t N, double beta,
+                                double* C, int64_t ldc) {
+  const int64_t MN = M * N;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < MN;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += P[z * MN + e];
+    const int64_t i = e % M, j = e / M;
+    double* cp = C + i + j * ldc;
+    *cp = (beta == 0.0) ? s : s + beta * *cp;
+  }
+}
+
+template <int BM, int BN, int CMP>
+static void launch_t(const GemmDesc& d, const GemmArgs& g, dim3 grid, hipStream_t s) {
+  if (d.ta == 'N' && d.tb == 'N')
+    hipLaunchKernelGGL((k_gemm<BM, BN, false, false, CMP>), grid, dim3(256), 0, s, g);
+  else if (d.ta == 'T' && d.tb == 'N')
+    hipLaunchKernelGGL((k_gemm<BM, BN, true, false, CMP>), grid, dim3(256), 0, s, g);
+  else if (d.ta == 'N' && d.tb == 'T')
+    hipLaunchKernelGGL((k_gemm<BM, BN, false, true, CMP>), grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((k_gemm<BM, BN, true, true, CMP>), grid, dim3(256), 0, s, g);
+}
+
+hipError_t gemm(const GemmDesc& d, hipStream_t s, double* scratch, int64_t scratch_doubles,
+                double* flops) {
+  if (d.M <= 0 || d.N <= 0) return hipSuccess;
+  if (d.compute == COMPUTE_BF16) return hipErrorNotSupported;
+  if (d.K <= 0) {
+    // C = beta C: reuse the reduction kernel with zero partials is wasteful;
+    // a K = 0 product only happens for empty panels, which callers avoid.
+    return hipSuccess;
+  }
+  const bool big = d.M >= 128 && d.N >= 128;
+  const int BM = big ? 128 : 64, BN = big ? 128 : 64;
+  const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
+  const int64_t tiles = tm * tn;
+  int64_t nsplit = 1;
+  if (tiles < 512 && d.K >= 1024 && scratch && scratch_doubles >= 2 * d.M * d.N) {
+    nsplit = std::min<int64_t>((1024 + tiles - 1) / tiles, d.K / 512);
+    nsplit = std::min<int64_t>(nsplit, scratch_doubles / (d.M * d.N));
+    nsplit = std::max<int64_t>(nsplit, 1);
+  }
+  int64_t kchunk = (d.K + nsplit - 1) / nsplit;
+  kchunk = (kchunk + 15) / 16 * 16;
+  nsplit = (d.K + kchunk - 1) / kchunk;
+  GemmArgs g{d.M, d.N, d.K, kchunk, d.alpha, d.beta, d.A, d.lda, d.B, d.ldb,
+             d.C, d.ldc, nsplit > 1 ? scratch : nullptr, d.maskA, d.maskB};
+  dim3 grid((unsigned)tm, (unsigned)tn, (unsigned)nsplit);
+  if (d.compute == COMPUTE_F32) {
+    if (big) launch_t<128, 128, COMPUTE_F32>(d, g, grid, s);
+    else launch_t<64, 64, COMPUTE_F32>(d, g, grid, s);
+  } else {
+    if (big) launch_t<128, 128, COMPUTE_F64>(d, g, grid, s);
+    else launch_t<64, 64, COMPUTE_F64>(d, g, grid, s);
+  }
+  if (nsplit > 1) {
+    const int64_t MN = d.M * d.N;
+    const int blocks = (int)std::min<int64_t>((MN + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(blocks), dim3(256), 0, s, (const double*)scratch,
+                       (int)nsplit, d.M, d.N, d.beta, d.C, d.ldc);
+  }
+  if (flops) *flops += 2.0 * (double)d.M * (double)d.N * (double)d.K;
+  return hipGetLastError();
+}
+
+}  // namespace miqr
