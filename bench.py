@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput of the tall-skinny QR hot path (TSQR / 1D-CAQR-EG base case with
+EG recursion above it) on one MI355X, FP64, with explicit thin Q and a
+least-squares solve on the factors.
+
+One step = factor a 1,048,576 x 64 and a 262,144 x 256 Gaussian matrix in place
+(each with its explicit thin Q), then solve one least-squares right-hand side
+with the 262,144 x 256 factors (apply Q^T, back substitution).  Every step works
+on its own copy of the inputs, prepared in HBM before the timed region.
+
+value = nominal QR flops (2 m n^2 - 2 n^3 / 3, summed over both matrices) per
+second.  The JSON line also carries the roofline of the dominant kernel
+(per-launch algorithmic bytes or flops over its average duration, from HIP
+events recorded around every library launch inside the timed region) and the
+CPU oracle timed on a bounded sample of the same workload.
+"""
+import argparse
+import hashlib
+import glob
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+SHAPES = [(1048576, 64), (262144, 256)]
+PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12}
+# kernel -> arithmetic unit its flops run on
+KERNEL_UNIT = {"gemm_f64": ("mfma", "fp64"), "gemm_f32": ("mfma", "fp32"),
+               "tsqr_down_leaf": ("mfma", "fp64"), "tsqr_down_tree": ("mfma", "fp64"),
+               "tsqr_chain_qr_leaf": ("alu", "fp64"), "tsqr_chain_qr_tree": ("alu", "fp64"),
+               "tsqr_hr_root": ("alu", "fp64"), "trsm_diag": ("alu", "fp64"),
+               "gemm_splitk_reduce": ("alu", "fp64")}
+
+
+def nominal_flops(m, n):
+    return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for p in sorted(glob.glob(os.path.join(ROOT, "paper_1805_05278_amd", "csrc", "*"))):
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def roofline(totals, steps):
+    name = max(totals, key=lambda k: totals[k]["ms"])
+    t = totals[name]
+    sec = t["ms"] * 1e-3 / t["launches"]
+    bytes_per = t["bytes"] / t["launches"]
+    flops_per = t["flops"] / t["launches"]
+    unit, prec = KERNEL_UNIT.get(name, ("alu", "fp64"))
+    peak_f = PEAK[prec]
+    # The binding roof is the lower of compute and bandwidth at this intensity.
+    if flops_per / max(bytes_per, 1.0) < peak_f / PEAK["hbm"]:
+        out = dict(bound="hbm", achieved=bytes_per / sec / 1e9, peak=PEAK["hbm"] / 1e9, unit="GB/s")
+    else:
+        out = dict(bound=unit, achieved=flops_per / sec / 1e12, peak=peak_f / 1e12, unit="TFLOP/s")
+    out["frac"] = out["achieved"] / out["peak"]
+    out["kernel"] = name
+    out["launches_per_step"] = t["launches"] / steps
+    out["avg_launch_ms"] = t["ms"] / t["launches"]
+    out["algorithmic_bytes_per_launch"] = bytes_per
+    out["algorithmic_flops_per_launch"] = flops_per
+    out["traffic"] = None
+    tf = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if os.path.exists(tf):
+        rec = json.load(open(tf)).get(name)
+        if rec and rec.get("source_digest") == source_digest():
+            out["traffic"] = rec["hbm_bytes_per_launch"]
+    return out
+
+
+def cpu_baseline(inputs):
+    """The oracle (plain unblocked Householder QR + T + thin Q, FP64, OpenMP over
+    trailing columns) on a bounded sample of the same two matrices."""
+    import numpy as np
+    import oracle
+    sample = [(262144, 64), (32768, 256)]
+    flops = 0.0
+    t0 = time.perf_counter()
+    for (ms, ns), A in zip(sample, inputs):
+        f = oracle.qr(np.asfortranarray(A[:ms, :ns]))
+        oracle.thin_q(f)
+        flops += nominal_flops(ms, ns)
+    dt = time.perf_counter() - t0
+    return {"value": flops / dt / 1e9, "unit": "GFLOP/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": "oracle QR + T + thin Q of the first 262144 rows of the 1048576x64 "
+                      "matrix and the first 32768 rows of the 262144x256 matrix (%.1f s)" % dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (PMC byte-counter scale)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_1805_05278_amd as miqr
+    import synth
+
+    dev = torch.device("cuda:0")
+    h = miqr.Handle(0)
+    host = [synth.gaussian(m, n, 2000 + i) for i, (m, n) in enumerate(SHAPES)]
+    pristine = [miqr.to_colmajor(A) for A in host]
+    m2, n2 = SHAPES[1]
+    xt = synth.rng(2100).standard_normal(n2)
+    b_host = host[1] @ xt + 1e-6 * synth.rng(2101).standard_normal(m2)
+    b_pristine = miqr.to_colmajor(b_host.reshape(-1, 1))
+
+    def fresh():
+        As = []
+        for P in pristine:
+            A = miqr.colmajor(*P.shape)
+            A.copy_(P)
+            As.append(A)
+        b = miqr.colmajor(m2, 1)
+        b.copy_(b_pristine)
+        return As, b
+
+    Ts = [miqr.colmajor(n, n) for (_, n) in SHAPES]
+    Qs = [miqr.colmajor(m, n) for (m, n) in SHAPES]
+    opts = [h.opts(Q=Q) for Q in Qs]
+
+    def step(As, b):
+        for A, T, o in zip(As, Ts, opts):
+            h.factor(A, T, o)
+        h.apply_q("T", As[1], Ts[1], b)
+        h.solve_r(As[1], b[:n2])
+
+    work = fresh()
+    for _ in range(args.warmup):
+        for A, P in zip(work[0], pristine):
+            A.copy_(P)
+        work[1].copy_(b_pristine)
+        step(*work)
+    torch.cuda.synchronize()
+    batches = [fresh() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+
+    if not args.no_profile:
+        h.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0.record()
+    for As, b in batches:
+        step(As, b)
+    e1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = e0.elapsed_time(e1) / args.steps
+    totals = h.profile_totals() if not args.no_profile else {}
+    h.profile(False)
+
+    # Spot check of the last step against simple invariants (not timed).
+    As, b = batches[-1]
+    R1 = torch.triu(As[0][:64, :64])
+    Qr = Qs[0]
+    rec = float(torch.linalg.norm(Qr[:4096] @ R1 - pristine[0][:4096]) /
+                torch.linalg.norm(pristine[0][:4096]))
+
+    if args.copy_calibration:
+        x = torch.empty(1 << 27, dtype=torch.float64, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
+        torch.cuda.synchronize()
+
+    flops = sum(nominal_flops(m, n) for m, n in SHAPES)
+    value = flops / (ms * 1e-3) / 1e9
+    line = {
+        "metric": "QR GFLOP/s (nominal 2mn^2-2n^3/3, FP64, tall-skinny TSQR/1D-CAQR-EG with thin Q + LS solve)",
+        "value": value,
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: i.i.d. N(0,1) from numpy PCG64 seeds 2000/2001",
+        "config": {"workload": "tall-skinny QR + thin Q: 1048576x64 and 262144x256, "
+                               "plus one least-squares RHS on the 262144x256 factors",
+                   "fraction_of_fp64_peak": value * 1e9 / PEAK["fp64"],
+                   "wall_s": wall, "recon_err_top4096": rec},
+    }
+    if totals:
+        line["roofline"] = roofline(totals, args.steps)
+        line["kernels"] = {k: {"ms_per_step": v["ms"] / args.steps,
+                               "launches_per_step": v["launches"] / args.steps}
+                           for k, v in sorted(totals.items(), key=lambda kv: -kv[1]["ms"])}
+    if not args.no_cpu:
+        line["cpu_baseline"] = cpu_baseline(host)
+    print(json.dumps(line))
+    h.close()
+
+
+if __name__ == "__main__":
+    main()

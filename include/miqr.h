@@ -116,6 +116,20 @@ int64_t qr_workspace_size(int64_t m, int64_t n, const qr_opts *opts);
  * more than the nominal count). */
 double miqr_last_gemm_flops(miqr_handle handle);
 
+/* Per-kernel timing.  While enabled (enable != 0, which also clears earlier
+ * totals) every kernel the handle's entry points launch is bracketed by two
+ * HIP events on its stream, and its algorithmic HBM bytes and flops are
+ * recorded.  miqr_profile_kernels synchronises the pending events and returns
+ * the number of distinct kernel names; miqr_profile_get reads entry `index`
+ * (name copied into `name`, NUL-terminated, at most name_len bytes): total
+ * milliseconds, launch count, total bytes and flops.  Any output pointer may
+ * be NULL.  The events add a few microseconds per launch. */
+miqr_status miqr_profile_enable(miqr_handle handle, int enable);
+int miqr_profile_kernels(miqr_handle handle);
+miqr_status miqr_profile_get(miqr_handle handle, int index, char *name,
+                             int name_len, double *ms, int64_t *launches,
+                             double *bytes, double *flops);
+
 /* QR factorisation in place (Alg. 2 with the TSQR base case of Sec. 6.1).
  *   A  (m x n, lda >= m, m >= n >= 1): on return R in the upper triangle and
  *      V's strict lower trapezoid below it.

@@ -80,6 +80,15 @@ def lib():
         L.qr_solve_r.restype = st
         L.miqr_last_gemm_flops.argtypes = [_vp]
         L.miqr_last_gemm_flops.restype = ctypes.c_double
+        L.miqr_profile_enable.argtypes = [_vp, ctypes.c_int]
+        L.miqr_profile_enable.restype = st
+        L.miqr_profile_kernels.argtypes = [_vp]
+        L.miqr_profile_kernels.restype = ctypes.c_int
+        L.miqr_profile_get.argtypes = [_vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_int,
+                                       ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64),
+                                       ctypes.POINTER(ctypes.c_double),
+                                       ctypes.POINTER(ctypes.c_double)]
+        L.miqr_profile_get.restype = st
         _lib = L
     return _lib
 
@@ -154,6 +163,25 @@ class Handle:
     @property
     def last_gemm_flops(self) -> float:
         return float(lib().miqr_last_gemm_flops(self._h))
+
+    def profile(self, enable: bool = True):
+        """Start (clearing earlier totals) or stop per-kernel event timing."""
+        self._check(lib().miqr_profile_enable(self._h, 1 if enable else 0))
+
+    def profile_totals(self) -> dict:
+        """{kernel: dict(ms, launches, bytes, flops)} accumulated while enabled."""
+        n = lib().miqr_profile_kernels(self._h)
+        out = {}
+        for i in range(n):
+            name = ctypes.create_string_buffer(128)
+            ms, fl, by = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+            cnt = _i64()
+            self._check(lib().miqr_profile_get(self._h, i, name, 128, ctypes.byref(ms),
+                                               ctypes.byref(cnt), ctypes.byref(by),
+                                               ctypes.byref(fl)))
+            out[name.value.decode()] = dict(ms=ms.value, launches=cnt.value, bytes=by.value,
+                                            flops=fl.value)
+        return out
 
     @staticmethod
     def opts(b=0, leaf_rows=0, chain=0, arity=0, precision=FP64, normalize=False,

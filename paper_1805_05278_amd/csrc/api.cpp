@@ -12,6 +12,7 @@
 #include "common.h"
 #include "gemm.h"
 #include "miqr.h"
+#include "profiler.h"
 #include "solve.h"
 #include "tsqr.h"
 
@@ -24,7 +25,21 @@ struct miqr_ctx {
   int* dflag = nullptr;
   std::string err;
   double gemm_flops = 0.0;  // multiply-add flops of the GEMMs launched by the last call
+  bool profiling = false;
+  KernelTimer timer;
+  std::vector<std::string> prof_names;
 };
+
+namespace {
+// Points the launch-site timer at the handle for the duration of an entry point.
+struct ProfScope {
+  KernelTimer* prev;
+  explicit ProfScope(miqr_handle h) : prev(g_timer) {
+    g_timer = (h && h->profiling) ? &h->timer : nullptr;
+  }
+  ~ProfScope() { g_timer = prev; }
+};
+}  // namespace
 
 namespace {
 
@@ -74,7 +89,7 @@ struct Tuning {
   int64_t b = 64;
   int leaf_rows = 0;
   int chain = 0;
-  int arity = 2;
+  int arity = 0;  // 0: widest node the stacked-R buffer allows (capped at 5)
 };
 
 Tuning tuning_from(const qr_opts* o, int64_t m, int64_t n) {
@@ -346,9 +361,41 @@ int64_t qr_workspace_size(int64_t m, int64_t n, const qr_opts* o) {
 
 double miqr_last_gemm_flops(miqr_handle h) { return h ? h->gemm_flops : 0.0; }
 
+miqr_status miqr_profile_enable(miqr_handle h, int enable) {
+  if (!h) return MIQR_EINVAL;
+  if (enable) h->timer.clear();
+  h->profiling = enable != 0;
+  return MIQR_OK;
+}
+
+int miqr_profile_kernels(miqr_handle h) {
+  if (!h) return 0;
+  h->timer.collect();
+  h->prof_names.clear();
+  for (auto& kv : h->timer.totals) h->prof_names.push_back(kv.first);
+  return (int)h->prof_names.size();
+}
+
+miqr_status miqr_profile_get(miqr_handle h, int index, char* name, int name_len, double* ms,
+                             int64_t* launches, double* bytes, double* flops) {
+  if (!h || index < 0 || index >= (int)h->prof_names.size()) return MIQR_EINVAL;
+  const std::string& k = h->prof_names[index];
+  const KernelTotals& t = h->timer.totals[k];
+  if (name && name_len > 0) {
+    std::strncpy(name, k.c_str(), (size_t)name_len - 1);
+    name[name_len - 1] = 0;
+  }
+  if (ms) *ms = t.ms;
+  if (launches) *launches = t.launches;
+  if (bytes) *bytes = t.bytes;
+  if (flops) *flops = t.flops;
+  return MIQR_OK;
+}
+
 miqr_status qr_factor(miqr_handle h, void* stream, int64_t m, int64_t n, double* A, int64_t lda,
                       double* T, int64_t ldt, const qr_opts* o) {
   if (!h) return MIQR_EINVAL;
+  ProfScope prof_scope(h);
   h->err.clear();
   if (n < 1 || m < n) return fail(h, MIQR_EINVAL, "need m >= n >= 1");
   if (lda < m || ldt < n) return fail(h, MIQR_EINVAL, "leading dimension too small");
@@ -373,6 +420,7 @@ miqr_status qr_apply_q(miqr_handle h, void* stream, char trans, int64_t m, int64
                        const double* VR, int64_t lda, const double* T, int64_t ldt, double* C,
                        int64_t ldc) {
   if (!h) return MIQR_EINVAL;
+  ProfScope prof_scope(h);
   h->err.clear();
   if (trans != 'N' && trans != 'T') return fail(h, MIQR_EINVAL, "trans must be 'N' or 'T'");
   if (n < 1 || m < n || k < 0) return fail(h, MIQR_EINVAL, "need m >= n >= 1, k >= 0");
@@ -394,6 +442,7 @@ miqr_status qr_form_q(miqr_handle h, void* stream, int64_t m, int64_t n, const d
                       int64_t lda, const double* T, int64_t ldt, const double* sign, double* Q,
                       int64_t ldq) {
   if (!h) return MIQR_EINVAL;
+  ProfScope prof_scope(h);
   if (n < 1 || m < n) return fail(h, MIQR_EINVAL, "need m >= n >= 1");
   if (lda < m || ldt < n || ldq < m) return fail(h, MIQR_EINVAL, "leading dimension too small");
   if (bad_ptr(VR) || bad_ptr(T) || bad_ptr(Q)) return fail(h, MIQR_EINVAL, "null pointer");
@@ -432,6 +481,7 @@ miqr_status qr_form_q(miqr_handle h, void* stream, int64_t m, int64_t n, const d
 miqr_status qr_solve_r(miqr_handle h, void* stream, int64_t n, int64_t nrhs, const double* VR,
                        int64_t lda, double* X, int64_t ldx) {
   if (!h) return MIQR_EINVAL;
+  ProfScope prof_scope(h);
   if (n < 1 || nrhs < 0 || lda < n || ldx < n) return fail(h, MIQR_EINVAL, "bad sizes");
   if (bad_ptr(VR) || bad_ptr(X)) return fail(h, MIQR_EINVAL, "null pointer");
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
@@ -454,6 +504,7 @@ miqr_status qr_solve_r(miqr_handle h, void* stream, int64_t n, int64_t nrhs, con
 miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t nrhs, double* A,
                      int64_t lda, double* B, int64_t ldb, const qr_opts* o, qr_info* info) {
   if (!h) return MIQR_EINVAL;
+  ProfScope prof_scope(h);
   h->err.clear();
   if (n < 1 || m < n || nrhs < 1) return fail(h, MIQR_EINVAL, "need m >= n >= 1, nrhs >= 1");
   if (lda < m || ldb < m) return fail(h, MIQR_EINVAL, "leading dimension too small");

@@ -13,6 +13,10 @@ constexpr int kNB = 64;
 constexpr int kTS = kNB * kNB;
 constexpr int kBS = kNB * 2 * kNB;
 constexpr int kMaxLevels = 40;
+// A TSQR tree node stacks the R factors of its children (after the first)
+// into at most kYL rows; its basis Y takes kYS doubles (leading dim kYL).
+constexpr int kYL = 256;
+constexpr int kYS = kYL * kNB;
 
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
@@ -25,9 +29,31 @@ __device__ __forceinline__ d4 mfma64(double a, double b, d4 acc) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
 }
 
+// Cross-lane moves through DPP (no LDS round trip).  A double moves as two
+// 32-bit halves.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  int lo = (int)(unsigned)(b & 0xffffffffull), hi = (int)(unsigned)(b >> 32);
+  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, true);
+  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, true);
+  return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
+}
+
+// Sum over the 4 lanes of a quad (quad_perm [1,0,3,2] then [2,3,0,1]); every
+// lane of the quad receives the total.
 __device__ __forceinline__ double quad_sum(double v) {
-  v += __shfl_xor(v, 1);
-  v += __shfl_xor(v, 2);
+  v += dpp_mov<0xB1>(v);
+  v += dpp_mov<0x4E>(v);
+  return v;
+}
+
+// Sum over 8 consecutive lanes (quad sums, then row_half_mirror pairs the two
+// quads of each half-row).
+__device__ __forceinline__ double oct_sum(double v) {
+  v = quad_sum(v);
+  v += dpp_mov<0x141>(v);
   return v;
 }
 

@@ -21,6 +21,7 @@
 
 #include "common.h"
 #include "gemm.h"
+#include "profiler.h"
 
 namespace miqr {
 
@@ -162,23 +163,29 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __syncthreads();
   }
 
+  // Epilogue, one 16-row slice at a time: all C values of the slice are read
+  // before any of them is written, so the loads are issued together.
 #pragma unroll
   for (int a = 0; a < SA; ++a) {
     const int64_t i = i0 + wm * WM + 16 * a + li;
-    if (i >= g.M) continue;
+    const bool row_ok = i < g.M;
+    double cv[SB][4];
 #pragma unroll
     for (int b = 0; b < SB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
-        if (j >= g.N) continue;
+        cv[b][r] = (row_ok && j < g.N && !g.P && g.beta != 0.0) ? g.C[i + j * g.ldc] : 0.0;
+      }
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
+        if (!row_ok || j >= g.N) continue;
         const double v = g.alpha * (double)acc[a][b][r];
-        if (g.P) {
-          g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = v;
-        } else {
-          double* cp = g.C + i + j * g.ldc;
-          *cp = (g.beta == 0.0) ? v : v + g.beta * *cp;
-        }
+        if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = v;
+        else g.C[i + j * g.ldc] = v + g.beta * cv[b][r];
       }
   }
 }
@@ -233,15 +240,22 @@ hipError_t gemm(const GemmDesc& d, hipStream_t s, double* scratch, int64_t scrat
   GemmArgs g{d.M, d.N, d.K, kchunk, d.alpha, d.beta, d.A, d.lda, d.B, d.ldb,
              d.C, d.ldc, nsplit > 1 ? scratch : nullptr, d.maskA, d.maskB};
   dim3 grid((unsigned)tm, (unsigned)tn, (unsigned)nsplit);
-  if (d.compute == COMPUTE_F32) {
-    if (big) launch_t<128, 128, COMPUTE_F32>(d, g, grid, s);
-    else launch_t<64, 64, COMPUTE_F32>(d, g, grid, s);
-  } else {
-    if (big) launch_t<128, 128, COMPUTE_F64>(d, g, grid, s);
-    else launch_t<64, 64, COMPUTE_F64>(d, g, grid, s);
+  const double gbytes = 8.0 * ((double)d.M * d.K + (double)d.K * d.N +
+                               (d.beta == 0.0 ? 1.0 : 2.0) * (double)d.M * d.N);
+  {
+    TimedLaunch tl(s, d.compute == COMPUTE_F32 ? "gemm_f32" : "gemm_f64", gbytes,
+                   2.0 * (double)d.M * d.N * d.K);
+    if (d.compute == COMPUTE_F32) {
+      if (big) launch_t<128, 128, COMPUTE_F32>(d, g, grid, s);
+      else launch_t<64, 64, COMPUTE_F32>(d, g, grid, s);
+    } else {
+      if (big) launch_t<128, 128, COMPUTE_F64>(d, g, grid, s);
+      else launch_t<64, 64, COMPUTE_F64>(d, g, grid, s);
+    }
   }
   if (nsplit > 1) {
     const int64_t MN = d.M * d.N;
+    TimedLaunch tr(s, "gemm_splitk_reduce", 8.0 * (double)MN * (nsplit + 2), (double)MN * nsplit);
     const int blocks = (int)std::min<int64_t>((MN + 255) / 256, 4096);
     hipLaunchKernelGGL(k_splitk_reduce, dim3(blocks), dim3(256), 0, s, (const double*)scratch,
                        (int)nsplit, d.M, d.N, d.beta, d.C, d.ldc);

@@ -4,6 +4,7 @@
 
 #include "common.h"
 #include "gemm.h"
+#include "profiler.h"
 #include "solve.h"
 
 namespace miqr {
@@ -169,8 +170,12 @@ hipError_t solve_upper(hipStream_t s, int64_t n, int64_t nrhs, const double* R, 
   const int64_t nblk = (n + kNB - 1) / kNB;
   for (int64_t bk = nblk - 1; bk >= 0; --bk) {
     const int64_t i0 = bk * kNB, i1 = std::min<int64_t>(n, i0 + kNB);
-    hipLaunchKernelGGL(k_trsm_diag<false>, dim3(1), dim3(256), 0, s, (int)(i1 - i0), nrhs,
-                       R + i0 + i0 * ldr, ldr, X + i0, ldx);
+    {
+      TimedLaunch tl(s, "trsm_diag", 8.0 * (double)(i1 - i0) * (i1 - i0 + 2 * nrhs),
+                     (double)(i1 - i0) * (i1 - i0) * nrhs);
+      hipLaunchKernelGGL(k_trsm_diag<false>, dim3(1), dim3(256), 0, s, (int)(i1 - i0), nrhs,
+                         R + i0 + i0 * ldr, ldr, X + i0, ldx);
+    }
     if (i0 > 0) {
       GemmDesc d;
       d.ta = 'N';
@@ -199,8 +204,12 @@ hipError_t solve_upper_trans(hipStream_t s, int64_t n, int64_t nrhs, const doubl
   const int64_t nblk = (n + kNB - 1) / kNB;
   for (int64_t bk = 0; bk < nblk; ++bk) {
     const int64_t i0 = bk * kNB, i1 = std::min<int64_t>(n, i0 + kNB);
-    hipLaunchKernelGGL(k_trsm_diag<true>, dim3(1), dim3(256), 0, s, (int)(i1 - i0), nrhs,
-                       R + i0 + i0 * ldr, ldr, X + i0, ldx);
+    {
+      TimedLaunch tl(s, "trsm_diag", 8.0 * (double)(i1 - i0) * (i1 - i0 + 2 * nrhs),
+                     (double)(i1 - i0) * (i1 - i0) * nrhs);
+      hipLaunchKernelGGL(k_trsm_diag<true>, dim3(1), dim3(256), 0, s, (int)(i1 - i0), nrhs,
+                         R + i0 + i0 * ldr, ldr, X + i0, ldx);
+    }
     if (i1 < n) {
       GemmDesc d;
       d.ta = 'T';

@@ -3,120 +3,116 @@
 //
 // Reduction structure.  The panel's rows are split evenly into leaf blocks of
 // at most 128 or 256 rows (at least nbr rows each).  A workgroup reduces a
-// *chain* of consecutive blocks in sequence.  A leaf chain starts with the
-// local Householder QR of its first block (App. C.1); a tree chain starts from
-// its first child's R.  Every further step factors the stacked matrix [R; X_s]
-// with the next block X_s,
+// *chain* of consecutive leaf blocks in sequence: the first block gets a
+// local Householder QR of its own rows (App. C.1); every further block X_s is
+// stacked under the running R and the stacked matrix is factored,
 //     [R; X_s] = Q_s [R_new; 0],   Q_s = I - [I; Y_s] T_s [I; Y_s]^T,
-// which is the paper's local QR of stacked R factors (App. C.1) with the
-// block structure of the stacked triangle exploited: the reflector for column
-// j touches only row j of R and the rows of X_s.  The R factors of one level's
-// chains are the blocks of the next level, until one chain remains (a tree of
-// arity `arity` above chains of `chain` leaves; the paper's binomial tree is
-// arity 2 with chain 1).
+// with the structure of the stacked triangle exploited: the reflector for
+// column j touches only row j of R and the rows of X_s.  Above the leaves,
+// a tree node takes the R factors of up to `arity` children and performs the
+// same step once, with the R factors of children 1.. stacked into one X.  The
+// paper's binomial tree is arity 2 with one leaf block per chain; wider nodes
+// trade a larger local QR for fewer sequential levels (the paper's
+// latency/bandwidth parameter).
 //
-// Downsweep (App. C.2).  Starting from B at the root, each chain is walked
-// backwards: M = T_s B, block s receives -Y_s M, and B <- B - M; the first
-// child of a tree chain receives the remaining B, the first block of a leaf
-// chain receives [B; 0] - V M with M = Z B, Z = T V_top^T stored by the
-// factorisation.  Started from B = I this yields W, the leading columns of the
-// Q-factor.
+// Downsweep (App. C.2).  Starting from B at the root, a node hands
+// B - T B to its first child and -Y_s (T B) to the others; a leaf chain is
+// walked backwards (M = T_s B, block s receives -Y_s M, B <- B - M) and its
+// first block receives [B; 0] - V (Z B) with Z = T V_top^T stored by the
+// factorisation.  Started from B = I this yields W, the leading columns of
+// the Q-factor.
 //
 // Householder reconstruction (App. C.2).  The root workgroup follows the path
 // to leaf block 0 only, forms X (top rows of W), runs the sign-modified LU
 // X + S = L U, and returns T = U S L^{-T}, R = -S R_root, and U^{-1}.  The
-// downsweep proper then starts from [U^{-1}, -S D] so that one pass over the
-// leaves yields V = W U^{-1} and, optionally, the thin Q = -W S D (App. C.2's
-// remark that starting from U^{-1} saves the second broadcast).  The top rows
-// of V are L (written from the reconstruction), R replaces them above the
+// downsweep proper starts from [U^{-1}, -S D] so that one pass over the
+// leaves yields V = W U^{-1} and, optionally, the thin Q = -W S D (the
+// paper's remark that starting from U^{-1} saves the second broadcast).  The
+// top rows of V are L, written from the reconstruction, with R above the
 // diagonal.
 #include <algorithm>
 
 #include "common.h"
+#include "profiler.h"
 #include "tsqr.h"
 
 namespace miqr {
 
 struct ChainQRArgs {
-  double* X;        // leaf level: panel (in place); tree level: child R array
+  double* X;       // leaf level: panel (in place); tree level: child R array
   int64_t ldx;
-  int64_t xrows;    // leaf level: panel rows
+  int64_t xrows;   // leaf level: panel rows
   int nblocks, chain_len, nbr, leaf;
-  double* Y;        // tree levels: Y per block
-  double* T;        // per block
-  double* R;        // per chain
+  double* Y;       // tree levels: Y per node (kYS doubles, leading dim kYL)
+  double* T;       // leaf: per block; tree: per node
+  double* R;       // per chain / node
 };
 
-// Thread layout: t = 4 c + q.  Thread (c, q) holds column c of the current
-// block for rows r(e) = 8 (e / 2) + 2 q + (e % 2), e < RPT (4 RPT rows).
-template <int RPT>
-__global__ __launch_bounds__(256) void k_chain_qr(ChainQRArgs a) {
-  constexpr int H = 4 * RPT;
-  const int t = threadIdx.x, c = t >> 2, q = t & 3;
-  const int chain = blockIdx.x;
-  const int b0 = chain * a.chain_len;
-  const int b1 = min(b0 + a.chain_len, a.nblocks);
-  const int nbr = a.nbr;
-  __shared__ double Rs[kNB][kNB + 1];
-  __shared__ double Gs[kNB][kNB + 1];  // Gram entries y_c . y_j, then T in place
-  __shared__ __align__(16) double vbuf[2][H];
-  __shared__ double taus[kNB];
-
-  for (int i = t; i < kTS; i += 256) {
-    const int r = i % kNB, cc = i / kNB;
-    double v = 0.0;
-    if (!a.leaf && r < nbr && cc < nbr) v = a.X[(int64_t)b0 * kTS + i];
-    Rs[r][cc] = v;
+// Sum over N consecutive lanes (N = 16 or 32), result in every lane: quad
+// sums and half-row / row mirrors through DPP, then (N = 32) an exchange
+// between the two 16-lane rows of a 32-lane group through ds_swizzle.
+template <int N>
+__device__ __forceinline__ double group_sum(double v) {
+  v = oct_sum(v);
+  v += dpp_mov<0x140>(v);  // row_mirror: lane i <-> 15 - i
+  if (N == 32) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    int lo = __builtin_amdgcn_ds_swizzle((int)(unsigned)(b & 0xffffffffull), 0x401F);
+    int hi = __builtin_amdgcn_ds_swizzle((int)(unsigned)(b >> 32), 0x401F);
+    v += __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) |
+                                          (unsigned long long)(unsigned)lo));
   }
-  __syncthreads();
+  return v;
+}
 
-  double x[RPT];
-  for (int b = a.leaf ? b0 : b0 + 1; b < b1; ++b) {
-    int64_t rstart = 0;
-    int rows;
-    double* src;
-    int64_t ld;
-    if (a.leaf) {
-      rstart = ((int64_t)b * a.xrows) / a.nblocks;
-      rows = (int)((((int64_t)b + 1) * a.xrows) / a.nblocks - rstart);
-      src = a.X + rstart;
-      ld = a.ldx;
-    } else {
-      rows = nbr;
-      src = a.X + (int64_t)b * kTS;
-      ld = kNB;
-    }
+// Register layout of a block of H rows (H = 128 or 256) in a 512-thread
+// workgroup: RG = H / 8 row groups of 8 consecutive rows; thread t holds rows
+// 8 rg .. 8 rg + 7 (rg = t % RG) of CPT = RG / 8 columns cg CPT .. cg CPT +
+// CPT - 1 (cg = t / RG).  The RG threads of a column group sit in one wave,
+// so column sums are lane reductions.  Each reflector value read from LDS is
+// reused for CPT columns.
+template <int H>
+struct Lay {
+  static constexpr int RG = H / 8;
+  static constexpr int CPT = RG / 8;
+};
+
+// One QR step on the rows held in registers (x[u][s]: column cg CPT + u, row
+// 8 rg + s).
+//   first:  plain Householder QR of the rows themselves (pivot row j);
+//   !first: the rows are stacked under the upper triangular R held in Rs.
+// On return x holds the basis (rows below the pivot for `first`, all rows
+// otherwise), Rs the new R (for !first), Gs the kernel T in its upper
+// triangle (Gs must be zero below the diagonal and outside nbr on entry), and
+// taus the reflector scalars.
+template <int H, bool first>
+__device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
+                                        double (*Rs)[kNB + 1], double (*Gs)[kNB + 1],
+                                        double (*vbuf)[H], double* taus, double* Wt) {
+  constexpr int RG = Lay<H>::RG, CPT = Lay<H>::CPT;
+  const int t = threadIdx.x, rg = t % RG, cg = t / RG;
+  // Columns are taken CPT at a time so that the owner's register slot U is a
+  // compile-time index (a runtime slot would force x out of registers).
+  for (int j0 = 0; j0 < nbr; j0 += CPT) {
 #pragma unroll
-    for (int e = 0; e < RPT; ++e) {
-      const int r = 8 * (e >> 1) + 2 * q + (e & 1);
-      x[e] = (c < nbr && r < rows) ? src[r + (int64_t)c * ld] : 0.0;
-    }
-
-    // The first block of a leaf chain is a plain Householder QR of its own rows
-    // (the paper's local QR, App. C.1): reflector j pivots on row j of the
-    // block and leaves the rows above it (R) alone.  Later blocks are stacked
-    // under the running R.
-    const bool first = a.leaf && b == b0;
-    for (int j = 0; j < nbr; ++j) {
+    for (int U = 0; U < CPT; ++U) {
+      const int j = j0 + U;
+      if (j >= nbr) break;
       double* vb = vbuf[j & 1];
-      if (c == j) {
-        double ss = 0.0, alpha;
-        if (first) {
-          double av = 0.0;
+      if (cg == j0 / CPT) {
+        double s4[4] = {0.0, 0.0, 0.0, 0.0}, av = 0.0;
 #pragma unroll
-          for (int e = 0; e < RPT; ++e) {
-            const int r = 8 * (e >> 1) + 2 * q + (e & 1);
-            if (r > j) ss += x[e] * x[e];
-            if (r == j) av = x[e];
+        for (int s = 0; s < 8; ++s) {
+          const int r = 8 * rg + s;
+          if (first) {
+            s4[s & 3] += (r > j) ? x[U][s] * x[U][s] : 0.0;
+            av = (r == j) ? x[U][s] : av;
+          } else {
+            s4[s & 3] += x[U][s] * x[U][s];
           }
-          ss = quad_sum(ss);
-          alpha = quad_sum(av);
-        } else {
-#pragma unroll
-          for (int e = 0; e < RPT; ++e) ss += x[e] * x[e];
-          ss = quad_sum(ss);
-          alpha = Rs[j][j];
         }
+        const double ss = group_sum<RG>((s4[0] + s4[1]) + (s4[2] + s4[3]));
+        const double alpha = first ? group_sum<RG>(av) : Rs[j][j];
         double beta = alpha, tau = 0.0, scale = 1.0;
         if (ss != 0.0) {
           const double nrm = sqrt(alpha * alpha + ss);
@@ -124,132 +120,235 @@ __global__ __launch_bounds__(256) void k_chain_qr(ChainQRArgs a) {
           tau = (beta - alpha) / beta;
           scale = 1.0 / (alpha - beta);
         }
-        if (first) {
+        double nv[8];
 #pragma unroll
-          for (int e = 0; e < RPT; e += 2) {
-            double v[2];
+        for (int s = 0; s < 8; ++s) {
+          const int r = 8 * rg + s;
+          const double sc = x[U][s] * scale;
+          if (first) {
+            nv[s] = (r > j) ? sc : ((r == j) ? 1.0 : 0.0);
+            x[U][s] = (r > j) ? sc : ((r == j) ? beta : x[U][s]);
+          } else {
+            nv[s] = sc;
+            x[U][s] = sc;
+          }
+        }
 #pragma unroll
-            for (int u = 0; u < 2; ++u) {
-              const int r = 8 * (e >> 1) + 2 * q + u;
-              if (r > j) {
-                x[e + u] *= scale;
-                v[u] = x[e + u];
-              } else if (r == j) {
-                x[e + u] = beta;
-                v[u] = 1.0;
-              } else {
-                v[u] = 0.0;
-              }
-            }
-            *(double2*)&vb[8 * (e >> 1) + 2 * q] = make_double2(v[0], v[1]);
-          }
-          if (q == 0) taus[j] = tau;
-        } else {
-#pragma unroll
-          for (int e = 0; e < RPT; e += 2) {
-            x[e] *= scale;
-            x[e + 1] *= scale;
-            *(double2*)&vb[8 * (e >> 1) + 2 * q] = make_double2(x[e], x[e + 1]);
-          }
-          if (q == 0) {
-            Rs[j][j] = beta;
-            taus[j] = tau;
-          }
+        for (int s = 0; s < 8; s += 2)
+          *(double2*)&vb[8 * rg + s] = make_double2(nv[s], nv[s + 1]);
+        if (rg == 0) {
+          taus[j] = tau;
+          if (!first) Rs[j][j] = beta;
         }
       }
       __syncthreads();
-      if (c < nbr && c != j) {
-        double d = 0.0;
+      double v[8];
 #pragma unroll
-        for (int e = 0; e < RPT; e += 2) {
-          const double2 v = *(const double2*)&vb[8 * (e >> 1) + 2 * q];
-          d += v.x * x[e] + v.y * x[e + 1];
+      for (int s = 0; s < 8; s += 2) {
+        const double2 p = *(const double2*)&vb[8 * rg + s];
+        v[s] = p.x;
+        v[s + 1] = p.y;
+      }
+      double d[CPT];
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int s = 0; s < 8; s += 2) {
+          a0 += v[s] * x[u][s];
+          a1 += v[s + 1] * x[u][s + 1];
         }
-        d = quad_sum(d);
-        if (c > j) {
-          const double w = taus[j] * (first ? d : d + Rs[j][c]);
+        d[u] = a0 + a1;
+      }
 #pragma unroll
-          for (int e = 0; e < RPT; e += 2) {
-            const double2 v = *(const double2*)&vb[8 * (e >> 1) + 2 * q];
-            x[e] -= v.x * w;
-            x[e + 1] -= v.y * w;
-          }
-          if (q == 0 && !first) Rs[j][c] -= w;
-        } else if (q == 0) {
-          Gs[c][j] = d;  // v_c . v_j for c < j
+      for (int u = 0; u < CPT; ++u) d[u] = group_sum<RG>(d[u]);
+      const double tau = taus[j];
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int c = cg * CPT + u;
+        if (c > j && c < nbr) {
+          const double w = tau * (first ? d[u] : d[u] + Rs[j][c]);
+#pragma unroll
+          for (int s = 0; s < 8; ++s) x[u][s] -= v[s] * w;
+          if (rg == 0 && !first) Rs[j][c] -= w;
+        } else if (c < j && rg == 0) {
+          Gs[c][j] = d[u];  // v_c . v_j
         }
       }
+    }
+  }
+  __syncthreads();
+
+  // T from the Gram entries G (strict upper part of Gs) and tau (Sec. 2.3:
+  // T^{-1} = striu(V^T V) + diag(tau)^{-1}), built blockwise in place: first
+  // the 8 x 8 diagonal blocks by the column recurrence
+  // T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j], then blocks of 8, 16, 32 are
+  // paired, T12 = -T1 (G12 T2).
+  if (t < kNB) Gs[t][t] = (t < nbr) ? taus[t] : 0.0;
+  __syncthreads();
+  for (int jj = 1; jj < 8; ++jj) {
+    const int bb = t >> 3, i = t & 7;
+    const int col = 8 * bb + jj, row = 8 * bb + i;
+    const bool act = t < kNB && i < jj && col < nbr;
+    double s = 0.0;
+    if (act)
+      for (int k = i; k < jj; ++k) s += Gs[row][8 * bb + k] * Gs[8 * bb + k][col];
+    __syncthreads();
+    if (act) Gs[row][col] = -taus[col] * s;
+    __syncthreads();
+  }
+  for (int sz = 8; sz < kNB; sz *= 2) {
+    const int npair = kNB / (2 * sz);
+    for (int e = t; e < npair * sz * sz; e += 512) {
+      const int pr = e / (sz * sz), i = (e / sz) % sz, k = e % sz;
+      const int a = 2 * sz * pr, b = a + sz;
+      double s = 0.0;
+      for (int m = 0; m <= k; ++m) s += Gs[a + i][b + m] * Gs[b + m][b + k];
+      Wt[e] = s;
     }
     __syncthreads();
-
-    // T_s from the Gram entries, column by column over G's upper triangle:
-    // T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j], T_jj = tau_j.
-    for (int j = 0; j < nbr; ++j) {
-      const int i = t >> 2, p = t & 3;
+    for (int e = t; e < npair * sz * sz; e += 512) {
+      const int pr = e / (sz * sz), i = (e / sz) % sz, k = e % sz;
+      const int a = 2 * sz * pr, b = a + sz;
       double s = 0.0;
-      if (i < j) {
-        for (int k = i + p; k < j; k += 4) s += Gs[i][k] * Gs[k][j];
-        s = quad_sum(s);
-      }
-      __syncthreads();
-      if (p == 0) {
-        if (i < j) Gs[i][j] = -taus[j] * s;
-        else if (i == j) Gs[j][j] = taus[j];
-      }
-      __syncthreads();
-    }
-
-    double* ydst;
-    int64_t ldy;
-    if (a.leaf) {
-      ydst = src;
-      ldy = ld;
-    } else {
-      ydst = a.Y + (int64_t)b * kTS;
-      ldy = kNB;
-    }
-    if (c < nbr) {
-#pragma unroll
-      for (int e = 0; e < RPT; ++e) {
-        const int r = 8 * (e >> 1) + 2 * q + (e & 1);
-        if (r < rows) ydst[r + (int64_t)c * ldy] = x[e];
-      }
-    }
-    if (!first) {
-      for (int i = t; i < kTS; i += 256) {
-        const int r = i % kNB, cc = i / kNB;
-        a.T[(int64_t)b * kTS + i] = (r <= cc && cc < nbr) ? Gs[r][cc] : 0.0;
-      }
-    } else {
-      // Store Z = T V_top^T (upper triangular) in place of T, V_top the unit
-      // lower top nbr x nbr part of the block's V, so that the downsweep and
-      // the reconstruction apply this block as M = Z B, out = [B; 0] - V M.
-      // Rs (unused by the first block) holds V_top row-major for the product.
-#pragma unroll
-      for (int e = 0; e < RPT; ++e) {
-        const int r = 8 * (e >> 1) + 2 * q + (e & 1);
-        if (r < kNB && c < kNB) Rs[r][c] = (r > c) ? x[e] : ((r == c) ? 1.0 : 0.0);
-      }
-      __syncthreads();
-      for (int i = t; i < kTS; i += 256) {
-        const int r = i % kNB, cc = i / kNB;
-        double z = 0.0;
-        if (r <= cc && cc < nbr)
-          for (int k = r; k <= cc; ++k) z += Gs[r][k] * Rs[cc][k];
-        a.T[(int64_t)b * kTS + i] = z;
-      }
-      __syncthreads();
-      // The block's R (upper triangle of its top rows) seeds the chain.
-#pragma unroll
-      for (int e = 0; e < RPT; ++e) {
-        const int r = 8 * (e >> 1) + 2 * q + (e & 1);
-        if (r < kNB && c < kNB) Rs[r][c] = (r <= c && c < nbr) ? x[e] : 0.0;
-      }
+      for (int m = i; m < sz; ++m) s += Gs[a + i][a + m] * Wt[pr * sz * sz + m * sz + k];
+      Gs[a + i][b + k] = -s;
     }
     __syncthreads();
   }
+}
 
-  for (int i = t; i < kTS; i += 256) {
+template <int H>
+__global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
+  constexpr int RG = Lay<H>::RG, CPT = Lay<H>::CPT;
+  const int t = threadIdx.x, rg = t % RG, cg = t / RG;
+  const int chain = blockIdx.x;
+  const int b0 = chain * a.chain_len;
+  const int b1 = min(b0 + a.chain_len, a.nblocks);
+  const int nbr = a.nbr;
+  __shared__ double Rs[kNB][kNB + 1];
+  __shared__ double Gs[kNB][kNB + 1];
+  __shared__ __align__(16) double vbuf[2][H];
+  __shared__ double taus[kNB];
+  __shared__ double Wt[32 * kNB / 2];
+
+  for (int i = t; i < kTS; i += 512) {
+    const int r = i % kNB, cc = i / kNB;
+    double v = 0.0;
+    if (!a.leaf && r < nbr && cc < nbr) v = a.X[(int64_t)b0 * kTS + i];
+    Rs[r][cc] = v;
+    Gs[r][cc] = 0.0;
+  }
+  __syncthreads();
+
+  double x[CPT][8];
+  if (a.leaf) {
+    for (int b = b0; b < b1; ++b) {
+      const bool first = b == b0;
+      const int64_t rstart = ((int64_t)b * a.xrows) / a.nblocks;
+      const int rows = (int)((((int64_t)b + 1) * a.xrows) / a.nblocks - rstart);
+      double* src = a.X + rstart + 8 * rg;
+      const int64_t ld = a.ldx;
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int c = cg * CPT + u;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+          x[u][s] = (c < nbr && 8 * rg + s < rows) ? src[s + (int64_t)c * ld] : 0.0;
+      }
+      if (first) qr_step<H, true>(x, nbr, Rs, Gs, vbuf, taus, Wt);
+      else qr_step<H, false>(x, nbr, Rs, Gs, vbuf, taus, Wt);
+#pragma unroll
+      for (int u = 0; u < CPT; ++u) {
+        const int c = cg * CPT + u;
+#pragma unroll
+        for (int s = 0; s < 8; ++s)
+          if (c < nbr && 8 * rg + s < rows) src[s + (int64_t)c * ld] = x[u][s];
+      }
+      double* Tb = a.T + (int64_t)b * kTS;
+      if (!first) {
+        for (int i = t; i < kTS; i += 512) {
+          const int r = i % kNB, cc = i / kNB;
+          Tb[i] = (r <= cc && cc < nbr) ? Gs[r][cc] : 0.0;
+        }
+      } else {
+        // Z = T V_top^T (upper triangular) in place of T; Rs holds V_top
+        // (unit lower top nbr x nbr part of the block's basis) meanwhile.
+        if (rg < kNB / 8) {
+#pragma unroll
+          for (int u = 0; u < CPT; ++u) {
+            const int c = cg * CPT + u;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+              const int r = 8 * rg + s;
+              Rs[r][c] = (r > c) ? x[u][s] : ((r == c) ? 1.0 : 0.0);
+            }
+          }
+        }
+        __syncthreads();
+        for (int i = t; i < kTS; i += 512) {
+          const int r = i % kNB, cc = i / kNB;
+          double z = 0.0;
+          if (r <= cc && cc < nbr)
+            for (int k = r; k <= cc; ++k) z += Gs[r][k] * Rs[cc][k];
+          Tb[i] = z;
+        }
+        __syncthreads();
+        // The block's R (upper triangle of its top rows) seeds the chain.
+        if (rg < kNB / 8) {
+#pragma unroll
+          for (int u = 0; u < CPT; ++u) {
+            const int c = cg * CPT + u;
+#pragma unroll
+            for (int s = 0; s < 8; ++s) {
+              const int r = 8 * rg + s;
+              Rs[r][c] = (r <= c && c < nbr) ? x[u][s] : 0.0;
+            }
+          }
+        }
+      }
+      __syncthreads();
+    }
+  } else if (b1 - b0 >= 2) {
+    // Tree node: children b0+1 .. b1-1 stacked (row stride nbr) under R_{b0}.
+    const int rows = (b1 - b0 - 1) * nbr;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int c = cg * CPT + u;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int r = 8 * rg + s;
+        double v = 0.0;
+        if (c < nbr && r < rows) {
+          const int sidx = r / nbr, rr = r - sidx * nbr;
+          v = a.X[(int64_t)(b0 + 1 + sidx) * kTS + rr + c * kNB];
+        }
+        x[u][s] = v;
+      }
+    }
+    qr_step<H, false>(x, nbr, Rs, Gs, vbuf, taus, Wt);
+    double* Yn = a.Y + (int64_t)chain * kYS;
+#pragma unroll
+    for (int u = 0; u < CPT; ++u) {
+      const int c = cg * CPT + u;
+#pragma unroll
+      for (int s = 0; s < 8; ++s) {
+        const int r = 8 * rg + s;
+        if (c < nbr && r < rows) Yn[r + c * kYL] = x[u][s];
+      }
+    }
+    double* Tn = a.T + (int64_t)chain * kTS;
+    for (int i = t; i < kTS; i += 512) {
+      const int r = i % kNB, cc = i / kNB;
+      Tn[i] = (r <= cc && cc < nbr) ? Gs[r][cc] : 0.0;
+    }
+    __syncthreads();
+  } else {
+    double* Tn = a.T + (int64_t)chain * kTS;
+    for (int i = t; i < kTS; i += 512) Tn[i] = 0.0;
+  }
+
+  for (int i = t; i < kTS; i += 512) {
     const int r = i % kNB, cc = i / kNB;
     a.R[(int64_t)chain * kTS + i] = (r <= cc && cc < nbr) ? Rs[r][cc] : 0.0;
   }
@@ -260,33 +359,46 @@ struct HRArgs {
   const double* T[kMaxLevels];
   int nblocks[kMaxLevels];
   int chain_len[kMaxLevels];
-  const double* Rtop;    // R of the single chain of the top level
-  const double* A0;      // leaf block 0 (its Y, in place), leading dim lda
+  const double* Rtop;    // R of the top node
+  const double* A0;      // leaf block 0 (its basis, in place), leading dim lda
   int64_t lda;
   int nbr, nq, normalize;
   double* Tp;            // nbr x nbr kernel, leading dim ldt
   int64_t ldt;
   double* LR;            // kTS: strict lower L, upper R
-  double* Broot;         // kBS: downsweep input of the top chain
+  double* Broot;         // kBS: downsweep input of the top node
   double* sign;          // optional, nbr doubles
 };
 
-// C = A_glob (upper triangular, column-major, ld kNB) * B  (nbr x nbr), all in LDS except A.
-__device__ void hr_tri_mul(double (*C)[kNB + 1], const double* A, double (*B)[kNB + 1], int nbr) {
+// C = A B with A upper triangular (global, column-major, ld kNB) and B in LDS;
+// A is staged through S first.  All nbr x nbr, 256 threads.
+__device__ void hr_tri_mul(double (*C)[kNB + 1], const double* A, double (*B)[kNB + 1],
+                           double (*S)[kNB + 1], int nbr) {
   const int t = threadIdx.x;
-  const int cc = t & 63, i0 = (t >> 6) * 16;
-  for (int i = i0; i < i0 + 16; ++i) {
-    double s = 0.0;
-    if (i < nbr && cc < nbr)
-      for (int k = i; k < nbr; ++k) s += A[i + k * kNB] * B[k][cc];
-    C[i][cc] = s;
+  for (int i = t; i < kTS; i += 256) {
+    const int r = i % kNB, cc = i / kNB;
+    S[r][cc] = (r < nbr && cc < nbr) ? A[i] : 0.0;
   }
+  __syncthreads();
+  const int cc = t & 63, i0 = (t >> 6) * 16;
+  double acc[16];
+#pragma unroll
+  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
+  for (int k = i0; k < nbr; ++k) {
+    const double bk = B[k][cc];
+#pragma unroll
+    for (int u = 0; u < 16; ++u)
+      if (i0 + u <= k) acc[u] += S[i0 + u][k] * bk;
+  }
+#pragma unroll
+  for (int u = 0; u < 16; ++u) C[i0 + u][cc] = acc[u];
 }
 
 __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
   __shared__ double Bm[kNB][kNB + 1];
   __shared__ double Mm[kNB][kNB + 1];
   __shared__ double Xm[kNB][kNB + 1];
+  __shared__ double Sm[kNB][kNB + 1];
   __shared__ double Sv[kNB], Dv[kNB];
   const int t = threadIdx.x;
   const int nbr = a.nbr;
@@ -295,12 +407,22 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
     Bm[r][cc] = (r == cc && r < nbr) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // Walk the path from the root to leaf block 0 (child 0 of every chain 0).
-  for (int lev = a.L; lev >= 0; --lev) {
-    const int b1 = min(a.chain_len[lev], a.nblocks[lev]);
-    const double* T = a.T[lev];
+  // Tree path: node 0 of every level hands B - T B to its first child.
+  for (int lev = a.L; lev >= 1; --lev) {
+    if (min(a.chain_len[lev], a.nblocks[lev]) < 2) continue;
+    hr_tri_mul(Mm, a.T[lev], Bm, Sm, nbr);
+    __syncthreads();
+    for (int i = t; i < kTS; i += 256) {
+      const int r = i % kNB, cc = i / kNB;
+      Bm[r][cc] -= Mm[r][cc];
+    }
+    __syncthreads();
+  }
+  // Leaf chain 0, blocks b1-1 .. 1 (stacked steps).
+  {
+    const int b1 = min(a.chain_len[0], a.nblocks[0]);
     for (int b = b1 - 1; b >= 1; --b) {
-      hr_tri_mul(Mm, T + (int64_t)b * kTS, Bm, nbr);
+      hr_tri_mul(Mm, a.T[0] + (int64_t)b * kTS, Bm, Sm, nbr);
       __syncthreads();
       for (int i = t; i < kTS; i += 256) {
         const int r = i % kNB, cc = i / kNB;
@@ -309,23 +431,26 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
       __syncthreads();
     }
   }
-  // Leaf block 0 (a local QR with basis V and stored Z = T V_top^T):
+  // Leaf block 0 (local QR with basis V, stored Z = T V_top^T):
   // X = top rows of [B; 0] - V (Z B).
-  hr_tri_mul(Mm, a.T[0], Bm, nbr);
+  hr_tri_mul(Mm, a.T[0], Bm, Sm, nbr);
+  __syncthreads();
+  for (int i = t; i < kTS; i += 256) {
+    const int r = i % kNB, cc = i / kNB;
+    Sm[r][cc] = (r > cc && r < nbr && cc < nbr) ? a.A0[r + (int64_t)cc * a.lda] : 0.0;
+  }
   __syncthreads();
   {
     const int cc = t & 63, i0 = (t >> 6) * 16;
     for (int i = i0; i < i0 + 16; ++i) {
-      double s = 0.0;
-      if (i < nbr && cc < nbr) {
-        for (int k = 0; k < i; ++k) s += a.A0[i + (int64_t)k * a.lda] * Mm[k][cc];
-        s += Mm[i][cc];
-      }
+      double s = Mm[i][cc];
+      for (int k = 0; k < i; ++k) s += Sm[i][k] * Mm[k][cc];
       Xm[i][cc] = (i < nbr && cc < nbr) ? Bm[i][cc] - s : 0.0;
     }
   }
   __syncthreads();
-  // Sign-modified LU without pivoting: S_jj = sgn(X^_jj) (+1 for >= 0), X^_jj += S_jj.
+  // Sign-modified LU without pivoting: S_jj = sgn(X^_jj) (+1 for >= 0),
+  // X^_jj += S_jj, then eliminate below the pivot.
   for (int j = 0; j < nbr; ++j) {
     if (t == 0) {
       const double s = (Xm[j][j] >= 0.0) ? 1.0 : -1.0;
@@ -350,14 +475,14 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
   __syncthreads();
   for (int s = 1; s < nbr; ++s) {
     const int cc = t >> 2, p = t & 3;
-    const int il = s;             // L^{-1} row il, columns cc < il
+    const int il = s;
     if (cc < il) {
       double acc = 0.0;
       for (int k = cc + p; k < il; k += 4) acc += Xm[il][k] * Bm[k][cc];
       acc = quad_sum(acc);
       if (p == 0) Bm[il][cc] = -acc;
     }
-    const int iu = nbr - 1 - s;   // U^{-1} row iu, columns iu < cc < nbr
+    const int iu = nbr - 1 - s;
     if (cc > iu && cc < nbr) {
       double acc = 0.0;
       for (int k = iu + 1 + p; k <= cc; k += 4) acc += Xm[iu][k] * Mm[k][cc];
@@ -401,11 +526,11 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
 }
 
 struct DownArgs {
-  const double* Bin;   // per chain of this level
-  double* Bout;        // tree levels: per block (= per chain of the level below)
-  const double* T;     // per block
-  const double* Y;     // tree levels: per block
-  double* A;           // leaf level: panel (Y in, V out), leading dim lda
+  const double* Bin;   // per chain (leaf) / node (tree) of this level
+  double* Bout;        // tree levels: per child (= per chain of the level below)
+  const double* T;     // leaf: per block; tree: per node
+  const double* Y;     // tree levels: per node
+  double* A;           // leaf level: panel (basis in, V out), leading dim lda
   int64_t lda, xrows;
   double* Q;           // leaf level, optional
   int64_t ldq;
@@ -413,15 +538,100 @@ struct DownArgs {
   int nblocks, chain_len, nbr, nq, leaf;
 };
 
+// M = T B into Ms (T upper triangular from global, B in Bs); wave w computes
+// rows [16w, 16w + 16) of M.  MFMA operand roles: A = T tile, B = B tile.
+template <int NQM>
+__device__ __forceinline__ void down_tb(const double* Tb, double (*Bs)[NQM + 4],
+                                        double (*Ms)[NQM + 4], int nbr, int CT) {
+  constexpr int CTM = NQM / 16;
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
+  d4 acc[CTM];
+#pragma unroll
+  for (int ct = 0; ct < CTM; ++ct) acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
+  const int i = 16 * w + li;
+  for (int kk = 4 * w; kk < 16; ++kk) {
+    const int k = 4 * kk + lk;
+    const double av = (i < nbr && k < nbr) ? Tb[i + k * kNB] : 0.0;
+#pragma unroll
+    for (int ct = 0; ct < CTM; ++ct)
+      if (ct < CT) acc[ct] = mfma64(av, Bs[k][16 * ct + li], acc[ct]);
+  }
+#pragma unroll
+  for (int ct = 0; ct < CTM; ++ct)
+    if (ct < CT)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) Ms[16 * w + lk + 4 * r][16 * ct + li] = acc[ct][r];
+}
+
+// Rows of one leaf block (or one node's stacked children) receive
+// -Y M (+ B on the top rows of a leaf chain's first block).
+template <int RT, int NQM>
+__device__ __forceinline__ void down_emit(const DownArgs& a, double (*Bs)[NQM + 4],
+                                          double (*Ms)[NQM + 4], const double* Yb, int64_t ldy,
+                                          int rows, bool first, int64_t rstart, bool top_block,
+                                          int b0, int CT) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
+  const int nbr = a.nbr, nq = a.nq;
+  double yf[RT][16];
+#pragma unroll
+  for (int s = 0; s < RT; ++s) {
+    const int row = 16 * (w + 4 * s) + li;
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+      const int k = 4 * kk + lk;
+      double v = (row < rows && k < nbr) ? Yb[row + (int64_t)k * ldy] : 0.0;
+      if (first && row <= k) v = (row == k && k < nbr) ? 1.0 : 0.0;
+      yf[s][kk] = v;
+    }
+  }
+  for (int ct0 = 0; ct0 < CT; ct0 += 2) {
+    d4 acc[RT][2];
+#pragma unroll
+    for (int s = 0; s < RT; ++s) acc[s][0] = acc[s][1] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 16; ++kk) {
+#pragma unroll
+      for (int g = 0; g < 2; ++g) {
+        const double af = Ms[4 * kk + lk][16 * (ct0 + g) + li];
+#pragma unroll
+        for (int s = 0; s < RT; ++s) acc[s][g] = mfma64(af, yf[s][kk], acc[s][g]);
+      }
+    }
+#pragma unroll
+    for (int s = 0; s < RT; ++s) {
+      const int row = 16 * (w + 4 * s) + li;
+      if (row >= rows) continue;
+#pragma unroll
+      for (int g = 0; g < 2; ++g)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int cc = 16 * (ct0 + g) + lk + 4 * r;
+          if (cc >= nq) continue;
+          double v = -acc[s][g][r];
+          if (first && row < nbr) v += Bs[row][cc];
+          if (a.leaf) {
+            if (cc < nbr) {
+              if (top_block && row < nbr) v = a.LR[row + cc * kNB];
+              a.A[rstart + row + (int64_t)cc * a.lda] = v;
+            } else if (a.Q) {
+              a.Q[rstart + row + (int64_t)(cc - nbr) * a.ldq] = v;
+            }
+          } else {
+            const int sidx = row / nbr, rr = row - sidx * nbr;
+            a.Bout[(int64_t)(b0 + 1 + sidx) * kBS + rr + cc * kNB] = v;
+          }
+        }
+    }
+  }
+}
+
 // RT: 16-row tiles per wave (block height 64 RT); NQM: max columns of B.
 template <int RT, int NQM>
 __global__ __launch_bounds__(256) void k_chain_down(DownArgs a) {
   constexpr int BLD = NQM + 4;
-  constexpr int CTM = NQM / 16;
   __shared__ __align__(16) double Bs[kNB][BLD];
   __shared__ __align__(16) double Ms[kNB][BLD];
-  const int t = threadIdx.x, w = t >> 6, l = t & 63;
-  const int li = l & 15, lk = l >> 4;
+  const int t = threadIdx.x;
   const int chain = blockIdx.x;
   const int b0 = chain * a.chain_len;
   const int b1 = min(b0 + a.chain_len, a.nblocks);
@@ -435,109 +645,33 @@ __global__ __launch_bounds__(256) void k_chain_down(DownArgs a) {
   }
   __syncthreads();
 
-  const int bfirst = a.leaf ? b0 : b0 + 1;
-  for (int b = b1 - 1; b >= bfirst; --b) {
-    const bool first = a.leaf && b == b0;
-    // M = T_b B (Z_b B for a leaf chain's first block): wave w computes rows
-    // [16w, 16w + 16).
-    {
-      const double* Tb = a.T + (int64_t)b * kTS;
-      d4 acc[CTM];
-#pragma unroll
-      for (int ct = 0; ct < CTM; ++ct) acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
-      const int i = 16 * w + li;
-      for (int kk = 4 * w; kk < 16; ++kk) {
-        const int k = 4 * kk + lk;
-        const double av = (i < nbr && k < nbr) ? Tb[i + k * kNB] : 0.0;
-#pragma unroll
-        for (int ct = 0; ct < CTM; ++ct)
-          if (ct < CT) acc[ct] = mfma64(av, Bs[k][16 * ct + li], acc[ct]);
-      }
-#pragma unroll
-      for (int ct = 0; ct < CTM; ++ct)
-        if (ct < CT)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) Ms[16 * w + lk + 4 * r][16 * ct + li] = acc[ct][r];
+  if (a.leaf) {
+    for (int b = b1 - 1; b >= b0; --b) {
+      const bool first = b == b0;
+      down_tb<NQM>(a.T + (int64_t)b * kTS, Bs, Ms, nbr, CT);
+      __syncthreads();
+      if (!first)
+        for (int i = t; i < kNB * NQM; i += 256) {
+          const int r = i / NQM, cc = i % NQM;
+          Bs[r][cc] -= Ms[r][cc];
+        }
+      const int64_t rstart = ((int64_t)b * a.xrows) / a.nblocks;
+      const int rows = (int)((((int64_t)b + 1) * a.xrows) / a.nblocks - rstart);
+      down_emit<RT, NQM>(a, Bs, Ms, a.A + rstart, a.lda, rows, first, rstart, b == 0, b0, CT);
+      __syncthreads();
     }
-    __syncthreads();
-    if (!first)
-      for (int i = t; i < kNB * NQM; i += 256) {
-        const int r = i / NQM, cc = i % NQM;
-        Bs[r][cc] -= Ms[r][cc];
-      }
-    // Block b receives -Y_b M.
-    {
-      int64_t rstart = 0;
-      int rows;
-      const double* Yb;
-      int64_t ldy;
-      if (a.leaf) {
-        rstart = ((int64_t)b * a.xrows) / a.nblocks;
-        rows = (int)((((int64_t)b + 1) * a.xrows) / a.nblocks - rstart);
-        Yb = a.A + rstart;
-        ldy = a.lda;
-      } else {
-        rows = nbr;
-        Yb = a.Y + (int64_t)b * kTS;
-        ldy = kNB;
-      }
-      double yf[RT][16];
-#pragma unroll
-      for (int s = 0; s < RT; ++s) {
-        const int row = 16 * (w + 4 * s) + li;
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-          const int k = 4 * kk + lk;
-          double v = (row < rows && k < nbr) ? Yb[row + (int64_t)k * ldy] : 0.0;
-          if (first && row <= k) v = (row == k && k < nbr) ? 1.0 : 0.0;
-          yf[s][kk] = v;
-        }
-      }
-      for (int ct0 = 0; ct0 < CT; ct0 += 2) {
-        d4 acc[RT][2];
-#pragma unroll
-        for (int s = 0; s < RT; ++s) acc[s][0] = acc[s][1] = d4{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int kk = 0; kk < 16; ++kk) {
-#pragma unroll
-          for (int g = 0; g < 2; ++g) {
-            const double af = Ms[4 * kk + lk][16 * (ct0 + g) + li];
-#pragma unroll
-            for (int s = 0; s < RT; ++s) acc[s][g] = mfma64(af, yf[s][kk], acc[s][g]);
-          }
-        }
-#pragma unroll
-        for (int s = 0; s < RT; ++s) {
-          const int row = 16 * (w + 4 * s) + li;
-          if (row >= rows) continue;
-#pragma unroll
-          for (int g = 0; g < 2; ++g)
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-              const int cc = 16 * (ct0 + g) + lk + 4 * r;
-              if (cc >= nq) continue;
-              double v = -acc[s][g][r];
-              if (first && row < nbr) v += Bs[row][cc];
-              if (a.leaf) {
-                if (cc < nbr) {
-                  if (b == 0 && row < nbr) v = a.LR[row + cc * kNB];
-                  a.A[rstart + row + (int64_t)cc * a.lda] = v;
-                } else if (a.Q) {
-                  a.Q[rstart + row + (int64_t)(cc - nbr) * a.ldq] = v;
-                }
-              } else {
-                a.Bout[(int64_t)b * kBS + row + cc * kNB] = v;
-              }
-            }
-        }
-      }
+  } else {
+    if (b1 - b0 >= 2) {
+      down_tb<NQM>(a.T + (int64_t)chain * kTS, Bs, Ms, nbr, CT);
+      __syncthreads();
+      down_emit<RT, NQM>(a, Bs, Ms, a.Y + (int64_t)chain * kYS, kYL, (b1 - b0 - 1) * nbr, false,
+                         0, false, b0, CT);
+      __syncthreads();
     }
-    __syncthreads();
-  }
-  if (!a.leaf) {
+    // First child: B - M (M is zero when the node has a single child).
     for (int i = t; i < kBS; i += 256) {
       const int r = i % kNB, cc = i / kNB;
-      a.Bout[(int64_t)b0 * kBS + i] = (r < nbr && cc < nq) ? Bs[r][cc] : 0.0;
+      a.Bout[(int64_t)b0 * kBS + i] = (r < nbr && cc < nq) ? Bs[r][cc] - Ms[r][cc] : 0.0;
     }
   }
 }
@@ -552,7 +686,10 @@ TsqrPlan tsqr_plan(int64_t rows, int nbr, int leaf_rows, int chain, int arity, d
   p.leaf_rows = leaf_rows;
   const int64_t P0 = std::max<int64_t>(1, (rows + leaf_rows - 1) / leaf_rows);
   if (chain <= 0) chain = (int)std::max<int64_t>(1, std::min<int64_t>(8, P0 / 1024));
-  if (arity < 2) arity = 2;
+  // A node stacks arity - 1 child R factors (nbr rows each) in kYL rows.
+  const int max_arity = 1 + kYL / std::max(nbr, 1);
+  if (arity < 2) arity = std::min(max_arity, 5);
+  arity = std::min(arity, max_arity);
   int64_t off = 0;
   auto take = [&](int64_t n) {
     double* ptr = ws ? ws + off : nullptr;
@@ -573,8 +710,12 @@ TsqrPlan tsqr_plan(int64_t rows, int nbr, int leaf_rows, int chain, int arity, d
   }
   for (size_t i = 0; i < p.levels.size(); ++i) {
     TsqrLevel& lv = p.levels[i];
-    lv.T = take((int64_t)lv.nblocks * kTS);
-    if (i > 0) lv.Y = take((int64_t)lv.nblocks * kTS);
+    if (i == 0) {
+      lv.T = take((int64_t)lv.nblocks * kTS);
+    } else {
+      lv.T = take((int64_t)lv.nchains * kTS);
+      lv.Y = take((int64_t)lv.nchains * kYS);
+    }
     lv.R = take((int64_t)lv.nchains * kTS);
     lv.B = take((int64_t)lv.nchains * kBS);
   }
@@ -587,19 +728,27 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
                        int64_t ldt, double* Q, int64_t ldq, int normalize, double* sign) {
   const int nbr = p.nbr;
   const int L = (int)p.levels.size() - 1;
+  const double tri = 8.0 * nbr * (nbr + 1) / 2.0;  // bytes of one packed triangle
+  const double pan = 8.0 * (double)p.rows * nbr;     // bytes of the panel
   // Upsweep.
   {
     const TsqrLevel& l0 = p.levels[0];
     ChainQRArgs a{P, ldp, p.rows, l0.nblocks, l0.chain_len, nbr, 1, nullptr, l0.T, l0.R};
+    // Read A, write V; write T per block and R per chain.  Flops: QR 2 m nb^2
+    // plus the Gram products for T, m nb^2.
+    TimedLaunch tl(s, "tsqr_chain_qr_leaf", 2.0 * pan + tri * (l0.nblocks + l0.nchains),
+                   3.0 * (double)p.rows * nbr * nbr);
     if (p.leaf_rows == 256)
-      hipLaunchKernelGGL(k_chain_qr<64>, dim3(l0.nchains), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_chain_qr<256>, dim3(l0.nchains), dim3(512), 0, s, a);
     else
-      hipLaunchKernelGGL(k_chain_qr<32>, dim3(l0.nchains), dim3(256), 0, s, a);
+      hipLaunchKernelGGL(k_chain_qr<128>, dim3(l0.nchains), dim3(512), 0, s, a);
   }
   for (int lev = 1; lev <= L; ++lev) {
     const TsqrLevel& lv = p.levels[lev];
     ChainQRArgs a{p.levels[lev - 1].R, kNB, 0, lv.nblocks, lv.chain_len, nbr, 0, lv.Y, lv.T, lv.R};
-    hipLaunchKernelGGL(k_chain_qr<16>, dim3(lv.nchains), dim3(256), 0, s, a);
+    TimedLaunch tl(s, "tsqr_chain_qr_tree", tri * (2.0 * lv.nblocks + 3.0 * lv.nchains),
+                   3.0 * (double)lv.nblocks * nbr * nbr * nbr);
+    hipLaunchKernelGGL(k_chain_qr<kYL>, dim3(lv.nchains), dim3(512), 0, s, a);
   }
   // Householder reconstruction at the root.
   const int nq = Q ? 2 * nbr : nbr;
@@ -622,6 +771,7 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     h.LR = p.LR;
     h.Broot = p.levels[L].B;
     h.sign = sign;
+    TimedLaunch tl(s, "tsqr_hr_root", tri * 8.0, 6.0 * (double)nbr * nbr * nbr * (L + 2));
     hipLaunchKernelGGL(k_tsqr_hr, dim3(1), dim3(256), 0, s, h);
   }
   // Downsweep through the tree levels, then the leaves.
@@ -637,10 +787,12 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     d.nbr = nbr;
     d.nq = nq;
     d.leaf = 0;
+    TimedLaunch tl(s, "tsqr_down_tree", 8.0 * nbr * nq * 2.0 * lv.nblocks + tri * 2.0 * lv.nblocks,
+                   3.0 * (double)lv.nblocks * nbr * nbr * nq);
     if (nq > kNB)
-      hipLaunchKernelGGL((k_chain_down<1, 128>), dim3(lv.nchains), dim3(256), 0, s, d);
+      hipLaunchKernelGGL((k_chain_down<4, 128>), dim3(lv.nchains), dim3(256), 0, s, d);
     else
-      hipLaunchKernelGGL((k_chain_down<1, 64>), dim3(lv.nchains), dim3(256), 0, s, d);
+      hipLaunchKernelGGL((k_chain_down<4, 64>), dim3(lv.nchains), dim3(256), 0, s, d);
   }
   {
     const TsqrLevel& l0 = p.levels[0];
@@ -658,6 +810,10 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     d.nbr = nbr;
     d.nq = nq;
     d.leaf = 1;
+    // Read the basis, write V (and Q); T per block.  Flops: 2 m nb nq for
+    // -Y M plus nb^2 nq per block for M = T B.
+    TimedLaunch tl(s, "tsqr_down_leaf", pan * (Q ? 3.0 : 2.0) + tri * l0.nblocks,
+                   2.0 * (double)p.rows * nbr * nq + (double)l0.nblocks * nbr * nbr * nq);
     if (p.leaf_rows == 256) {
       if (nq > kNB)
         hipLaunchKernelGGL((k_chain_down<4, 128>), dim3(l0.nchains), dim3(256), 0, s, d);
