@@ -18,7 +18,10 @@ ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH, "-I" + INCLUDE, "-I" + CSRC,
          "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
          # No packed-FP32 instructions anywhere in device code.
-         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+         "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # Keep MFMA accumulators in VGPRs: with the AGPR form the compiler
+         # copied every accumulator between register files on each K slice.
+         "-mllvm", "-amdgpu-mfma-vgpr-form=1"]
 
 
 def sources():

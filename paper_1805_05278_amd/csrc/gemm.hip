@@ -61,10 +61,82 @@ struct MfmaTraits<COMPUTE_F32> {
   static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
 
-__device__ __forceinline__ double apply_mask(double v, int64_t r, int64_t c, int mask) {
-  if (mask == MASK_UNIT_LOWER) return (r < c) ? 0.0 : ((r == c) ? 1.0 : v);
-  if (mask == MASK_UPPER) return (r > c) ? 0.0 : v;
-  return v;
+// Per-thread global->register staging of one BK-deep slice of op(A) (BM x BK)
+// or op(B)^T (BN x BK).  Element (i, k) of the slice is stored at
+// (i, k) -> p[i + k ld] when the operand runs along i (not transposed A,
+// transposed B) and at p[k + i ld] otherwise.  Each thread owns a fixed
+// (i, k) pattern and a pointer advanced by a constant per slice, so the hot
+// loop does no 64-bit multiplies.
+template <int BX, int BK, bool ALONG_I>
+struct SliceLoader {
+  static constexpr int L = BX * BK / 256;  // elements per thread
+  const double* p;                         // this thread's first element
+  int64_t step;                            // pointer advance per slice
+  int64_t estride;                         // distance between a thread's elements
+  int i, k;                                // position of the first element
+  int di, dk;                              // position delta between elements
+  __device__ void init(const double* base, int64_t ld, int64_t x0, int64_t kbeg, int t) {
+    if (ALONG_I) {
+      i = t % BX;
+      k = t / BX;
+      di = 0;
+      dk = 256 / BX;
+      p = base + (x0 + i) + (kbeg + k) * ld;
+      estride = (int64_t)dk * ld;
+      step = (int64_t)BK * ld;
+    } else {
+      k = t % BK;
+      i = t / BK;
+      di = 256 / BK;
+      dk = 0;
+      p = base + (kbeg + k) + (x0 + i) * ld;
+      estride = (int64_t)di * ld;
+      step = BK;
+    }
+  }
+  // Fast path: every element in range, no structure.
+  __device__ void load_fast(double (&r)[L]) const {
+#pragma unroll
+    for (int s = 0; s < L; ++s) r[s] = p[s * estride];
+  }
+  // General path: bounds (x < X, kk < kend) and structure mask on the stored
+  // (row, col) = along_i ? (x, kk) : (kk, x).
+  __device__ void load_checked(double (&r)[L], int64_t x0, int64_t X, int64_t k0, int64_t kend,
+                               int mask) const {
+#pragma unroll
+    for (int s = 0; s < L; ++s) {
+      const int64_t x = x0 + i + s * di, kk = k0 + k + s * dk;
+      double v = 0.0;
+      if (x < X && kk < kend) {
+        v = p[s * estride];
+        const int64_t row = ALONG_I ? x : kk, col = ALONG_I ? kk : x;
+        if (mask == MASK_UNIT_LOWER) v = (row < col) ? 0.0 : ((row == col) ? 1.0 : v);
+        else if (mask == MASK_UPPER) v = (row > col) ? 0.0 : v;
+      }
+      r[s] = v;
+    }
+  }
+  template <typename T, int LD>
+  __device__ void store(T (*S)[LD], const double (&r)[L]) const {
+#pragma unroll
+    for (int s = 0; s < L; ++s) S[k + s * dk][i + s * di] = (T)r[s];
+  }
+  __device__ void advance() { p += step; }
+};
+
+// Whether every element of a slice (rows x0 .. x0+BX-1 of op, k0 .. k0+BK-1)
+// is in range and unaffected by the structure mask.
+template <int BX, int BK, bool ALONG_I>
+__device__ __forceinline__ bool slice_is_plain(int64_t x0, int64_t X, int64_t k0, int64_t kend,
+                                               int mask) {
+  if (x0 + BX > X || k0 + BK > kend) return false;
+  // stored row/col ranges
+  const int64_t r0 = ALONG_I ? x0 : k0, r1 = ALONG_I ? x0 + BX - 1 : k0 + BK - 1;
+  const int64_t c0 = ALONG_I ? k0 : x0, c1 = ALONG_I ? k0 + BK - 1 : x0 + BX - 1;
+  if (mask == MASK_UNIT_LOWER) return r0 > c1;  // strictly below the diagonal
+  if (mask == MASK_UPPER) return r1 <= c0;      // on or above the diagonal
+  (void)r1; (void)c0;
+  return true;
 }
 
 template <int BM, int BN, bool TA, bool TB, int CMP>
@@ -75,14 +147,19 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   constexpr int BK = 16;
   constexpr int PAD = 1;
   constexpr int WM = BM / 2, WN = BN / 2, SA = WM / 16, SB = WN / 16;
-  constexpr int LA = BM * BK / 256, LB = BN * BK / 256;
-  __shared__ T As[BK][BM + PAD];
-  __shared__ T Bs[BK][BN + PAD];
+  // op(A) runs along i in memory when A is not transposed; op(B)^T (N x K)
+  // runs along j when B is transposed.
+  constexpr bool A_ALONG = !TA, B_ALONG = TB;
+  typedef SliceLoader<BM, BK, A_ALONG> LA_t;
+  typedef SliceLoader<BN, BK, B_ALONG> LB_t;
+  __shared__ T As[2][BK][BM + PAD];
+  __shared__ T Bs[2][BK][BN + PAD];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
   const int wm = w & 1, wn = w >> 1;
   const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
   const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
   const int64_t kend = min(g.K, kbeg + g.kchunk);
+  const int nslab = (int)((kend - kbeg + BK - 1) / BK);
 
   Acc acc[SA][SB];
 #pragma unroll
@@ -92,73 +169,45 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
 
-  double ra[LA], rb[LB];
-  auto loadA = [&](int64_t k0) {
-#pragma unroll
-    for (int s = 0; s < LA; ++s) {
-      const int idx = t + 256 * s;
-      const int i = TA ? idx / BK : idx % BM;
-      const int k = TA ? idx % BK : idx / BM;
-      const int64_t gi = i0 + i, gk = k0 + k;
-      double v = 0.0;
-      if (gi < g.M && gk < kend) {
-        const int64_t r = TA ? gk : gi, c = TA ? gi : gk;
-        v = apply_mask(g.A[r + c * g.lda], r, c, g.maskA);
-      }
-      ra[s] = v;
-    }
-  };
-  auto loadB = [&](int64_t k0) {
-#pragma unroll
-    for (int s = 0; s < LB; ++s) {
-      const int idx = t + 256 * s;
-      const int j = TB ? idx % BN : idx / BK;
-      const int k = TB ? idx / BN : idx % BK;
-      const int64_t gj = j0 + j, gk = k0 + k;
-      double v = 0.0;
-      if (gj < g.N && gk < kend) {
-        const int64_t r = TB ? gj : gk, c = TB ? gk : gj;
-        v = apply_mask(g.B[r + c * g.ldb], r, c, g.maskB);
-      }
-      rb[s] = v;
-    }
+  LA_t la;
+  LB_t lb;
+  la.init(g.A, g.lda, i0, kbeg, t);
+  lb.init(g.B, g.ldb, j0, kbeg, t);
+  double ra[LA_t::L], rb[LB_t::L];
+  auto fetch = [&](int64_t k0) {
+    if (slice_is_plain<BM, BK, A_ALONG>(i0, g.M, k0, kend, g.maskA)) la.load_fast(ra);
+    else la.load_checked(ra, i0, g.M, k0, kend, g.maskA);
+    if (slice_is_plain<BN, BK, B_ALONG>(j0, g.N, k0, kend, g.maskB)) lb.load_fast(rb);
+    else lb.load_checked(rb, j0, g.N, k0, kend, g.maskB);
+    la.advance();
+    lb.advance();
   };
 
-  if (kbeg < kend) {
-    loadA(kbeg);
-    loadB(kbeg);
+  if (nslab > 0) {
+    fetch(kbeg);
+    la.store(As[0], ra);
+    lb.store(Bs[0], rb);
   }
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BK) {
-#pragma unroll
-    for (int s = 0; s < LA; ++s) {
-      const int idx = t + 256 * s;
-      const int i = TA ? idx / BK : idx % BM;
-      const int k = TA ? idx % BK : idx / BM;
-      As[k][i] = (T)ra[s];
-    }
-#pragma unroll
-    for (int s = 0; s < LB; ++s) {
-      const int idx = t + 256 * s;
-      const int j = TB ? idx % BN : idx / BK;
-      const int k = TB ? idx / BN : idx % BK;
-      Bs[k][j] = (T)rb[s];
-    }
-    __syncthreads();
-    if (k0 + BK < kend) {
-      loadA(k0 + BK);
-      loadB(k0 + BK);
-    }
+  __syncthreads();
+  for (int it = 0; it < nslab; ++it) {
+    const int cur = it & 1;
+    const bool more = it + 1 < nslab;
+    if (more) fetch(kbeg + (int64_t)(it + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       T af[SA], bf[SB];
 #pragma unroll
-      for (int a = 0; a < SA; ++a) af[a] = As[4 * ks + lk][wm * WM + 16 * a + li];
+      for (int a = 0; a < SA; ++a) af[a] = As[cur][4 * ks + lk][wm * WM + 16 * a + li];
 #pragma unroll
-      for (int b = 0; b < SB; ++b) bf[b] = Bs[4 * ks + lk][wn * WN + 16 * b + li];
+      for (int b = 0; b < SB; ++b) bf[b] = Bs[cur][4 * ks + lk][wn * WN + 16 * b + li];
 #pragma unroll
       for (int a = 0; a < SA; ++a)
 #pragma unroll
         for (int b = 0; b < SB; ++b) acc[a][b] = Tr::mma(bf[b], af[a], acc[a][b]);
+    }
+    if (more) {
+      la.store(As[cur ^ 1], ra);
+      lb.store(Bs[cur ^ 1], rb);
     }
     __syncthreads();
   }

@@ -370,28 +370,37 @@ struct HRArgs {
   double* sign;          // optional, nbr doubles
 };
 
-// C = A B with A upper triangular (global, column-major, ld kNB) and B in LDS;
-// A is staged through S first.  All nbr x nbr, 256 threads.
-__device__ void hr_tri_mul(double (*C)[kNB + 1], const double* A, double (*B)[kNB + 1],
-                           double (*S)[kNB + 1], int nbr) {
-  const int t = threadIdx.x;
-  for (int i = t; i < kTS; i += 256) {
+// Stage an nbr x nbr column-major matrix (leading dim kNB) from global
+// memory into LDS (row-major), zero outside nbr.
+__device__ __forceinline__ void hr_stage(double (*S)[kNB + 1], const double* G, int nbr) {
+  for (int i = threadIdx.x; i < kTS; i += 256) {
     const int r = i % kNB, cc = i / kNB;
-    S[r][cc] = (r < nbr && cc < nbr) ? A[i] : 0.0;
+    S[r][cc] = (r < nbr && cc < nbr) ? G[i] : 0.0;
   }
-  __syncthreads();
-  const int cc = t & 63, i0 = (t >> 6) * 16;
-  double acc[16];
+}
+
+// C = A B for 64 x 64 matrices in LDS on FP64 MFMA; wave w computes rows
+// [16 w, 16 w + 16).  C must not alias A or B.  TB: read B transposed.
+template <bool TB>
+__device__ __forceinline__ void hr_mm(double (*C)[kNB + 1], double (*A)[kNB + 1],
+                                      double (*B)[kNB + 1]) {
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
+  d4 acc[4];
 #pragma unroll
-  for (int u = 0; u < 16; ++u) acc[u] = 0.0;
-  for (int k = i0; k < nbr; ++k) {
-    const double bk = B[k][cc];
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int kk = 0; kk < 16; ++kk) {
+    const double af = A[16 * w + li][4 * kk + lk];
 #pragma unroll
-    for (int u = 0; u < 16; ++u)
-      if (i0 + u <= k) acc[u] += S[i0 + u][k] * bk;
+    for (int ct = 0; ct < 4; ++ct) {
+      const double bf = TB ? B[16 * ct + li][4 * kk + lk] : B[4 * kk + lk][16 * ct + li];
+      acc[ct] = mfma64(af, bf, acc[ct]);
+    }
   }
 #pragma unroll
-  for (int u = 0; u < 16; ++u) C[i0 + u][cc] = acc[u];
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) C[16 * w + lk + 4 * r][16 * ct + li] = acc[ct][r];
 }
 
 __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
@@ -399,7 +408,8 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
   __shared__ double Mm[kNB][kNB + 1];
   __shared__ double Xm[kNB][kNB + 1];
   __shared__ double Sm[kNB][kNB + 1];
-  __shared__ double Sv[kNB], Dv[kNB];
+  __shared__ double Sv[kNB], Dv[kNB], Ui[kNB];
+  __shared__ double pinv;
   const int t = threadIdx.x;
   const int nbr = a.nbr;
   for (int i = t; i < kTS; i += 256) {
@@ -407,89 +417,109 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
     Bm[r][cc] = (r == cc && r < nbr) ? 1.0 : 0.0;
   }
   __syncthreads();
-  // Tree path: node 0 of every level hands B - T B to its first child.
-  for (int lev = a.L; lev >= 1; --lev) {
-    if (min(a.chain_len[lev], a.nblocks[lev]) < 2) continue;
-    hr_tri_mul(Mm, a.T[lev], Bm, Sm, nbr);
+  // B <- B - T B for the T of every node on the path to leaf block 0 and for
+  // the stacked steps of leaf chain 0.
+  auto path_step = [&](const double* Tg) {
+    hr_stage(Sm, Tg, nbr);
+    __syncthreads();
+    hr_mm<false>(Mm, Sm, Bm);
     __syncthreads();
     for (int i = t; i < kTS; i += 256) {
       const int r = i % kNB, cc = i / kNB;
       Bm[r][cc] -= Mm[r][cc];
     }
     __syncthreads();
-  }
-  // Leaf chain 0, blocks b1-1 .. 1 (stacked steps).
+  };
+  for (int lev = a.L; lev >= 1; --lev)
+    if (min(a.chain_len[lev], a.nblocks[lev]) >= 2) path_step(a.T[lev]);
   {
     const int b1 = min(a.chain_len[0], a.nblocks[0]);
-    for (int b = b1 - 1; b >= 1; --b) {
-      hr_tri_mul(Mm, a.T[0] + (int64_t)b * kTS, Bm, Sm, nbr);
-      __syncthreads();
-      for (int i = t; i < kTS; i += 256) {
-        const int r = i % kNB, cc = i / kNB;
-        Bm[r][cc] -= Mm[r][cc];
-      }
-      __syncthreads();
-    }
+    for (int b = b1 - 1; b >= 1; --b) path_step(a.T[0] + (int64_t)b * kTS);
   }
   // Leaf block 0 (local QR with basis V, stored Z = T V_top^T):
   // X = top rows of [B; 0] - V (Z B).
-  hr_tri_mul(Mm, a.T[0], Bm, Sm, nbr);
+  hr_stage(Sm, a.T[0], nbr);
+  __syncthreads();
+  hr_mm<false>(Mm, Sm, Bm);
   __syncthreads();
   for (int i = t; i < kTS; i += 256) {
     const int r = i % kNB, cc = i / kNB;
-    Sm[r][cc] = (r > cc && r < nbr && cc < nbr) ? a.A0[r + (int64_t)cc * a.lda] : 0.0;
+    double v = 0.0;
+    if (r < nbr && cc < nbr) v = (r > cc) ? a.A0[r + (int64_t)cc * a.lda] : ((r == cc) ? 1.0 : 0.0);
+    Sm[r][cc] = v;
   }
   __syncthreads();
-  {
-    const int cc = t & 63, i0 = (t >> 6) * 16;
-    for (int i = i0; i < i0 + 16; ++i) {
-      double s = Mm[i][cc];
-      for (int k = 0; k < i; ++k) s += Sm[i][k] * Mm[k][cc];
-      Xm[i][cc] = (i < nbr && cc < nbr) ? Bm[i][cc] - s : 0.0;
-    }
+  hr_mm<false>(Xm, Sm, Mm);
+  __syncthreads();
+  for (int i = t; i < kTS; i += 256) {
+    const int r = i % kNB, cc = i / kNB;
+    Xm[r][cc] = (r < nbr && cc < nbr) ? Bm[r][cc] - Xm[r][cc] : 0.0;
+    Bm[r][cc] = (r == cc) ? 1.0 : 0.0;  // becomes L^{-1}
+    Mm[r][cc] = (r == cc) ? 1.0 : 0.0;  // becomes U^{-1}
   }
   __syncthreads();
-  // Sign-modified LU without pivoting: S_jj = sgn(X^_jj) (+1 for >= 0),
-  // X^_jj += S_jj, then eliminate below the pivot.
+  // Sign-modified LU without pivoting (App. C.2): before eliminating column j,
+  // S_jj = sgn(X^_jj) (+1 for >= 0) and X^_jj += S_jj.  The row operations are
+  // applied to the identity alongside, which therefore ends as L^{-1}.
+  const int i = t >> 2, p = t & 3;
   for (int j = 0; j < nbr; ++j) {
     if (t == 0) {
-      const double s = (Xm[j][j] >= 0.0) ? 1.0 : -1.0;
-      Sv[j] = s;
-      Xm[j][j] += s;
+      const double sg = (Xm[j][j] >= 0.0) ? 1.0 : -1.0;
+      Sv[j] = sg;
+      Xm[j][j] += sg;
+      pinv = 1.0 / Xm[j][j];
     }
     __syncthreads();
-    const int i = t >> 2, p = t & 3;
     if (i > j && i < nbr) {
-      const double l = Xm[i][j] / Xm[j][j];
-      for (int k = j + 1 + p; k < nbr; k += 4) Xm[i][k] -= l * Xm[j][k];
+      const double l = Xm[i][j] * pinv;
+      double xj[16], xi[16], ej[16], ei[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int k = j + 1 + p + 4 * m;
+        const bool ok = k < nbr;
+        xj[m] = ok ? Xm[j][k] : 0.0;
+        xi[m] = ok ? Xm[i][k] : 0.0;
+        const int ke = p + 4 * m;
+        ej[m] = (ke <= j) ? Bm[j][ke] : 0.0;
+        ei[m] = (ke <= j) ? Bm[i][ke] : 0.0;
+      }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int k = j + 1 + p + 4 * m;
+        if (k < nbr) Xm[i][k] = xi[m] - l * xj[m];
+        const int ke = p + 4 * m;
+        if (ke <= j) Bm[i][ke] = ei[m] - l * ej[m];
+      }
       if (p == 0) Xm[i][j] = l;
     }
     __syncthreads();
   }
-  // Bm <- L^{-1} (unit lower), Mm <- U^{-1} (upper).
-  for (int i = t; i < kTS; i += 256) {
-    const int r = i % kNB, cc = i / kNB;
-    Bm[r][cc] = (r == cc) ? 1.0 : 0.0;
-    Mm[r][cc] = (r == cc && r < nbr) ? 1.0 / Xm[r][r] : 0.0;
-  }
+  // U^{-1} by backward elimination on [U | I]: rows above j lose
+  // (U[i][j] / U[j][j]) times row j; the rows are scaled by 1/U_ii at the end.
+  if (t < nbr) Ui[t] = 1.0 / Xm[t][t];
   __syncthreads();
-  for (int s = 1; s < nbr; ++s) {
-    const int cc = t >> 2, p = t & 3;
-    const int il = s;
-    if (cc < il) {
-      double acc = 0.0;
-      for (int k = cc + p; k < il; k += 4) acc += Xm[il][k] * Bm[k][cc];
-      acc = quad_sum(acc);
-      if (p == 0) Bm[il][cc] = -acc;
-    }
-    const int iu = nbr - 1 - s;
-    if (cc > iu && cc < nbr) {
-      double acc = 0.0;
-      for (int k = iu + 1 + p; k <= cc; k += 4) acc += Xm[iu][k] * Mm[k][cc];
-      acc = quad_sum(acc);
-      if (p == 0) Mm[iu][cc] = -acc / Xm[iu][iu];
+  for (int j = nbr - 1; j >= 1; --j) {
+    if (i < j) {
+      const double f = Xm[i][j] * Ui[j];
+      double fj[16], fi[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int k = j + p + 4 * m;
+        const bool ok = k < nbr;
+        fj[m] = ok ? Mm[j][k] : 0.0;
+        fi[m] = ok ? Mm[i][k] : 0.0;
+      }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int k = j + p + 4 * m;
+        if (k < nbr) Mm[i][k] = fi[m] - f * fj[m];
+      }
     }
     __syncthreads();
+  }
+  for (int e = t; e < kTS; e += 256) {
+    const int r = e % kNB, cc = e / kNB;
+    if (r < nbr && cc < nbr) Mm[r][cc] *= Ui[r];
   }
   // R = -S R_root, optional D = sign(diag R).
   if (t < nbr) {
@@ -499,29 +529,44 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
     if (a.sign) a.sign[t] = d;
   }
   __syncthreads();
-  for (int i = t; i < kTS; i += 256) {
-    const int r = i % kNB, cc = i / kNB;
-    double lr = 0.0, tv = 0.0;
-    if (r < nbr && cc < nbr) {
-      if (r > cc) {
-        lr = Xm[r][cc];
-      } else {
-        lr = -Dv[r] * Sv[r] * a.Rtop[r + cc * kNB];
-        // T = U S L^{-T}: T[r][cc] = sum_{k=r..cc} U[r][k] S_k Linv[cc][k]
-        for (int k = r; k <= cc; ++k) tv += Xm[r][k] * Sv[k] * Bm[cc][k];
-      }
-      a.Tp[r + cc * a.ldt] = tv;
-    }
-    a.LR[i] = lr;
+  // T = U S L^{-T}: stage U S (upper) and multiply by L^{-1} transposed.
+  for (int e = t; e < kTS; e += 256) {
+    const int r = e % kNB, cc = e / kNB;
+    Sm[r][cc] = (r <= cc && cc < nbr) ? Xm[r][cc] * Sv[cc] : 0.0;
   }
-  for (int i = t; i < kBS; i += 256) {
-    const int r = i % kNB, cc = i / kNB;
+  __syncthreads();
+  {
+    const int w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
+    d4 acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
+    for (int kk = 0; kk < 16; ++kk) {
+      const double af = Sm[16 * w + li][4 * kk + lk];
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) acc[ct] = mfma64(af, Bm[16 * ct + li][4 * kk + lk], acc[ct]);
+    }
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 16 * w + lk + 4 * r, cc = 16 * ct + li;
+        if (row < nbr && cc < nbr) a.Tp[row + cc * a.ldt] = (row <= cc) ? acc[ct][r] : 0.0;
+      }
+  }
+  for (int e = t; e < kTS; e += 256) {
+    const int r = e % kNB, cc = e / kNB;
+    double lr = 0.0;
+    if (r < nbr && cc < nbr) lr = (r > cc) ? Xm[r][cc] : -Dv[r] * Sv[r] * a.Rtop[r + cc * kNB];
+    a.LR[e] = lr;
+  }
+  for (int e = t; e < kBS; e += 256) {
+    const int r = e % kNB, cc = e / kNB;
     double v = 0.0;
     if (r < nbr && cc < a.nq) {
       if (cc < nbr) v = Mm[r][cc];
       else if (cc - nbr == r) v = -Sv[r] * Dv[r];
     }
-    a.Broot[i] = v;
+    a.Broot[e] = v;
   }
 }
 
