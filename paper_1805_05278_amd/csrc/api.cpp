@@ -305,6 +305,259 @@ miqr_status do_apply(miqr_handle h, hipStream_t s, char trans, int64_t m, int64_
   return MIQR_OK;
 }
 
+// beta(x) = max_c ||A^T r_c|| / (||A||_F (||A||_F ||x_c|| + ||r_c||)),
+// r = b - A x, all FP64 on the device (A0, B0 originals; X solutions).
+// R (m x k) and U (n x k) are scratch.  Synchronises the stream.
+double backward_error_dev(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A0,
+                          const double* B0, const double* X, int64_t ldx, double* Rr, double* U,
+                          double* nrm, double* sc, int64_t scn, hipError_t* err) {
+  copy_matrix(s, m, k, B0, m, Rr, m);
+  GemmDesc d;
+  d.ta = 'N'; d.tb = 'N'; d.M = m; d.N = k; d.K = n; d.alpha = -1.0; d.beta = 1.0;
+  d.A = A0; d.lda = m; d.B = X; d.ldb = ldx; d.C = Rr; d.ldc = m;
+  hipError_t e = gemm(d, s, sc, scn);
+  d = GemmDesc();
+  d.ta = 'T'; d.tb = 'N'; d.M = n; d.N = k; d.K = m;
+  d.A = A0; d.lda = m; d.B = Rr; d.ldb = m; d.C = U; d.ldc = n;
+  if (e == hipSuccess) e = gemm(d, s, sc, scn);
+  column_sumsq(s, m, k, Rr, m, nrm);
+  column_sumsq(s, n, k, U, n, nrm + k);
+  column_sumsq(s, n, k, X, ldx, nrm + 2 * k);
+  column_sumsq(s, m, n, A0, m, nrm + 3 * k);
+  std::vector<double> hn(3 * k + n);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(hn.data(), nrm, sizeof(double) * hn.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  *err = e;
+  if (e != hipSuccess) return 0.0;
+  double fa = 0.0;
+  for (int64_t j = 0; j < n; ++j) fa += hn[3 * k + j];
+  fa = std::sqrt(fa);
+  double worst = 0.0;
+  for (int64_t c = 0; c < k; ++c) {
+    const double rn = std::sqrt(hn[c]), gn = std::sqrt(hn[k + c]), xn = std::sqrt(hn[2 * k + c]);
+    const double den = fa * (fa * xn + rn);
+    worst = std::max(worst, den > 0 ? gn / den : 0.0);
+  }
+  return worst;
+}
+
+// Least squares with the mixed form: the factorisation runs with FP32/BF16
+// trailing updates; the solution is refined in FP64 by conjugate gradients on
+// min ||b - A R^{-1} y|| (CGLS, right preconditioner R, x = R^{-1} y), with
+// every residual taken against the FP64 original of A.  It refines until the
+// backward error beta(x) (worst right-hand side) is at most tol and has
+// stopped improving (below 4u, or less than halved by the last iteration), so
+// the result carries FP64 accuracy rather than just meeting the gate; it
+// fails over to the FP64 path if the gate is not met within maxit steps.
+struct MixedWs {
+  double *T, *A0, *B0, *Rinv, *X, *Rr, *S, *P, *Tv, *Qv, *U, *W1, *W2, *sc, *nrm, *coef;
+  int64_t scn;
+};
+
+miqr_status lstsq_fp64(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64_t k, double* A,
+                       int64_t lda, double* B, int64_t ldb, const qr_opts* o, double* T,
+                       double* W1, double* W2, double* sc, int64_t scn, qr_info* info);
+
+miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64_t k, double* A,
+                        int64_t lda, double* B, int64_t ldb, const qr_opts* o, int comp,
+                        qr_info* info) {
+  const Tuning tune = tuning_from(o, m, n);
+  FactorLayout L = factor_layout(m, n, tune);
+  const int64_t need = L.total + 2 * n * n + m * n + 3 * m * k + 7 * n * k + 8 * k + 64 * 16 + 256;
+  miqr_status st = ensure_ws(h, (size_t)need * sizeof(double));
+  if (st != MIQR_OK) return st;
+  Arena ar{(double*)h->ws};
+  ar.take(L.total);
+  MixedWs w;
+  w.T = ar.take(n * n);
+  w.Rinv = ar.take(n * n);
+  w.A0 = ar.take(m * n);
+  w.B0 = ar.take(m * k);
+  w.Rr = ar.take(m * k);
+  w.Qv = ar.take(m * k);
+  w.X = ar.take(n * k);
+  w.S = ar.take(n * k);
+  w.P = ar.take(n * k);
+  w.Tv = ar.take(n * k);
+  w.U = ar.take(n * k);
+  w.W1 = ar.take(n * k);
+  w.W2 = ar.take(n * k);
+  w.nrm = ar.take(4 * k + n + 8);
+  w.coef = ar.take(2 * k + 8);
+  {
+    Arena far{(double*)h->ws};
+    far.take(L.tsqr);
+    far.take(L.wa);
+    far.take(L.wb);
+    w.sc = far.take(L.scratch);
+    w.scn = L.scratch;
+  }
+  const double tol = 1e-13, floor = 4.0 * 0x1p-53;
+  const int maxit = 50;
+  copy_matrix(s, m, n, A, lda, w.A0, m);
+  copy_matrix(s, m, k, B, ldb, w.B0, m);
+  st = do_factor(h, s, m, n, A, lda, w.T, n, o, comp);
+  if (st != MIQR_OK) return st;
+  find_zero_diagonal(s, n, A, lda, h->dflag);
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed");
+  bool converged = false;
+  int iters = 0;
+  double worst = 0.0;
+  auto G = [&](char ta, int64_t M, int64_t N, int64_t K, double alpha, const double* Ap,
+               int64_t la, int ma, const double* Bp, int64_t lb, double beta, double* Cp,
+               int64_t lc) {
+    if (e != hipSuccess) return;
+    GemmDesc d;
+    d.ta = ta; d.tb = 'N'; d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
+    d.A = Ap; d.lda = la; d.maskA = ma; d.B = Bp; d.ldb = lb; d.C = Cp; d.ldc = lc;
+    e = gemm(d, s, w.sc, w.scn);
+  };
+  std::vector<double> hn(4 * k + n + 8), hc(2 * k + 8);
+  auto fetch_norms = [&](int cnt) {
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(hn.data(), w.nrm, sizeof(double) * cnt, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+  };
+  if (!flag) {
+    // R^{-1} (upper): solve R Z = I.
+    set_identity(s, n, n, w.Rinv, n);
+    e = solve_upper(s, n, n, A, lda, w.Rinv, n, w.sc, w.scn);
+    // x0 = R^{-1} (Q^T b)[0:n]
+    copy_matrix(s, m, k, w.B0, m, w.Rr, m);
+    if (e == hipSuccess) {
+      miqr_status s2 = do_apply(h, s, 'T', m, n, k, A, lda, w.T, n, w.Rr, m, w.W1, w.W2, w.sc, w.scn);
+      if (s2 != MIQR_OK) return s2;
+    }
+    G('N', n, k, n, 1.0, w.Rinv, n, MASK_UPPER, w.Rr, m, 0.0, w.X, n);
+    // ||A||_F
+    column_sumsq(s, m, n, w.A0, m, w.nrm + 4 * k);
+    fetch_norms(4 * k + n);
+    double fa = 0.0;
+    for (int64_t j = 0; j < n; ++j) fa += hn[4 * k + j];
+    fa = std::sqrt(fa);
+    // r = b - A x, u = A^T r, s = R^{-T} u, p = s
+    copy_matrix(s, m, k, w.B0, m, w.Rr, m);
+    G('N', m, k, n, -1.0, w.A0, m, MASK_NONE, w.X, n, 1.0, w.Rr, m);
+    G('T', n, k, m, 1.0, w.A0, m, MASK_NONE, w.Rr, m, 0.0, w.U, n);
+    G('T', n, k, n, 1.0, w.Rinv, n, MASK_UPPER, w.U, n, 0.0, w.S, n);
+    copy_matrix(s, n, k, w.S, n, w.P, n);
+    column_sumsq(s, n, k, w.S, n, w.nrm);
+    column_sumsq(s, n, k, w.U, n, w.nrm + k);
+    column_sumsq(s, n, k, w.X, n, w.nrm + 2 * k);
+    column_sumsq(s, m, k, w.Rr, m, w.nrm + 3 * k);
+    fetch_norms(4 * k);
+    std::vector<double> gam(k);
+    auto backward = [&]() {
+      worst = 0.0;
+      for (int64_t c = 0; c < k; ++c) {
+        const double un = std::sqrt(hn[k + c]), xn = std::sqrt(hn[2 * k + c]),
+                     rn = std::sqrt(hn[3 * k + c]);
+        const double den = fa * (fa * xn + rn);
+        worst = std::max(worst, den > 0 ? un / den : 0.0);
+      }
+    };
+    for (int64_t c = 0; c < k; ++c) gam[c] = hn[c];
+    backward();
+    double prev = worst;
+    auto settled = [&]() { return worst <= tol && (worst <= floor || worst > 0.5 * prev); };
+    bool done = worst <= floor;
+    while (!done && iters < maxit && e == hipSuccess) {
+      ++iters;
+      // t = R^{-1} p, q = A t, alpha = gamma / ||q||^2
+      G('N', n, k, n, 1.0, w.Rinv, n, MASK_UPPER, w.P, n, 0.0, w.Tv, n);
+      G('N', m, k, n, 1.0, w.A0, m, MASK_NONE, w.Tv, n, 0.0, w.Qv, m);
+      column_sumsq(s, m, k, w.Qv, m, w.nrm);
+      fetch_norms(k);
+      bool stop = false;
+      for (int64_t c = 0; c < k; ++c) {
+        hc[c] = (hn[c] > 0.0) ? gam[c] / hn[c] : 0.0;
+        if (hn[c] == 0.0) stop = true;
+      }
+      if (stop) break;
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(w.coef, hc.data(), sizeof(double) * k, hipMemcpyHostToDevice, s);
+      axpy_cols(s, n, k, 1.0, w.coef, w.Tv, n, w.X, n);
+      axpy_cols(s, m, k, -1.0, w.coef, w.Qv, m, w.Rr, m);
+      // u = A^T r, backward error, s = R^{-T} u, p = s + beta p
+      G('T', n, k, m, 1.0, w.A0, m, MASK_NONE, w.Rr, m, 0.0, w.U, n);
+      G('T', n, k, n, 1.0, w.Rinv, n, MASK_UPPER, w.U, n, 0.0, w.S, n);
+      column_sumsq(s, n, k, w.S, n, w.nrm);
+      column_sumsq(s, n, k, w.U, n, w.nrm + k);
+      column_sumsq(s, n, k, w.X, n, w.nrm + 2 * k);
+      column_sumsq(s, m, k, w.Rr, m, w.nrm + 3 * k);
+      fetch_norms(4 * k);
+      prev = worst;
+      backward();
+      if (settled()) break;
+      for (int64_t c = 0; c < k; ++c) {
+        hc[k + c] = (gam[c] > 0.0) ? hn[c] / gam[c] : 0.0;
+        gam[c] = hn[c];
+      }
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(w.coef + k, hc.data() + k, sizeof(double) * k, hipMemcpyHostToDevice, s);
+      xpby_cols(s, n, k, w.S, n, w.coef + k, w.P, n);
+    }
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed");
+  converged = !flag && worst <= tol;
+  if (converged) {
+    copy_matrix(s, n, k, w.X, n, B, ldb);
+    if (info) {
+      info->iterations = iters;
+      info->fallback = 0;
+      info->precision_used = o ? o->precision : MIQR_FP64;
+      info->backward_error = worst;
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed");
+    return MIQR_OK;
+  }
+  // Fallback: refactor the original in FP64.
+  copy_matrix(s, m, n, w.A0, m, A, lda);
+  copy_matrix(s, m, k, w.B0, m, B, ldb);
+  qr_opts o64 = o ? *o : qr_opts{};
+  o64.precision = MIQR_FP64;
+  st = lstsq_fp64(h, s, m, n, k, A, lda, B, ldb, &o64, w.T, w.W1, w.W2, w.sc, w.scn, info);
+  if (info) {
+    info->iterations = iters;
+    info->fallback = 1;
+  }
+  if (st != MIQR_OK) return st;
+  if (info) {
+    info->backward_error = backward_error_dev(s, m, n, k, w.A0, w.B0, B, ldb, w.Rr, w.U, w.nrm,
+                                              w.sc, w.scn, &e);
+    if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed fallback");
+  }
+  return fail(h, MIQR_ENOCONV, "refinement did not reach 1e-13; FP64 result returned");
+}
+
+// FP64 least squares on the factors: factor, c = Q^T b, back substitution.
+miqr_status lstsq_fp64(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64_t k, double* A,
+                       int64_t lda, double* B, int64_t ldb, const qr_opts* o, double* T,
+                       double* W1, double* W2, double* sc, int64_t scn, qr_info* info) {
+  miqr_status st = do_factor(h, s, m, n, A, lda, T, n, o, COMPUTE_F64);
+  if (st != MIQR_OK) return st;
+  st = do_apply(h, s, 'T', m, n, k, A, lda, T, n, B, ldb, W1, W2, sc, scn);
+  if (st != MIQR_OK) return st;
+  find_zero_diagonal(s, n, A, lda, h->dflag);
+  int flag = 0;
+  hipError_t e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq");
+  if (flag) {
+    if (info) info->singular_index = flag;
+    return fail(h, MIQR_ESINGULAR, "R(" + std::to_string(flag - 1) + ") == 0");
+  }
+  e = solve_upper(s, n, k, A, lda, B, ldb, sc, scn);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq solve");
+  if (info) info->precision_used = MIQR_FP64;
+  return MIQR_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -517,7 +770,11 @@ miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t 
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   if (info) std::memset(info, 0, sizeof(*info));
-  if (prec != MIQR_FP64) return fail(h, MIQR_ENOTSUP, "mixed precision lstsq not built yet");
+  if (prec != MIQR_FP64) {
+    const int comp = prec == MIQR_MIXED_FP32 ? COMPUTE_F32 : COMPUTE_BF16;
+    miqr_status st = lstsq_mixed(h, s, m, n, nrhs, A, lda, B, ldb, o, comp, info);
+      return st;
+  }
 
   // Layout: factorisation workspace first, then T, W1, W2, and (for info) copies.
   const Tuning tune = tuning_from(o, m, n);

@@ -121,6 +121,13 @@ struct SliceLoader {
 #pragma unroll
     for (int s = 0; s < L; ++s) S[k + s * dk][i + s * di] = (T)r[s];
   }
+  // i-major store (S[i][k]), used for BF16 tiles whose MFMA fragments are
+  // 8 consecutive k values.
+  template <typename T, int LD>
+  __device__ void store_t(T (*S)[LD], const double (&r)[L]) const {
+#pragma unroll
+    for (int s = 0; s < L; ++s) S[i + s * di][k + s * dk] = (T)r[s];
+  }
   __device__ void advance() { p += step; }
 };
 
@@ -239,6 +246,97 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   }
 }
 
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+
+// BF16 inputs (FP64 operands rounded when staged), FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16.  One MFMA k-step per 32-deep slice; tiles are
+// stored i-major so that a lane's fragment (8 consecutive k) is one 16-byte
+// LDS read.  Fragment layout: a = A[l % 16][8 (l / 16) + e],
+// b = B[8 (l / 16) + e][l % 16], acc[r] = D[4 (l / 16) + r][l % 16].
+template <int BM, int BN, bool TA, bool TB>
+__global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
+  constexpr int BK = 32, KP = BK + 8;
+  constexpr int WM = BM / 2, WN = BN / 2, SA = WM / 16, SB = WN / 16;
+  constexpr bool A_ALONG = !TA, B_ALONG = TB;
+  typedef SliceLoader<BM, BK, A_ALONG> LA_t;
+  typedef SliceLoader<BN, BK, B_ALONG> LB_t;
+  __shared__ __align__(16) __bf16 As[2][BM][KP];
+  __shared__ __align__(16) __bf16 Bs[2][BN][KP];
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
+  const int wm = w & 1, wn = w >> 1;
+  const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
+  const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+  const int64_t kend = min(g.K, kbeg + g.kchunk);
+  const int nslab = (int)((kend - kbeg + BK - 1) / BK);
+  f4 acc[SA][SB];
+#pragma unroll
+  for (int a = 0; a < SA; ++a)
+#pragma unroll
+    for (int b = 0; b < SB; ++b) acc[a][b] = f4{0.f, 0.f, 0.f, 0.f};
+  LA_t la;
+  LB_t lb;
+  la.init(g.A, g.lda, i0, kbeg, t);
+  lb.init(g.B, g.ldb, j0, kbeg, t);
+  double ra[LA_t::L], rb[LB_t::L];
+  auto fetch = [&](int64_t k0) {
+    if (slice_is_plain<BM, BK, A_ALONG>(i0, g.M, k0, kend, g.maskA)) la.load_fast(ra);
+    else la.load_checked(ra, i0, g.M, k0, kend, g.maskA);
+    if (slice_is_plain<BN, BK, B_ALONG>(j0, g.N, k0, kend, g.maskB)) lb.load_fast(rb);
+    else lb.load_checked(rb, j0, g.N, k0, kend, g.maskB);
+    la.advance();
+    lb.advance();
+  };
+  if (nslab > 0) {
+    fetch(kbeg);
+    la.store_t(As[0], ra);
+    lb.store_t(Bs[0], rb);
+  }
+  __syncthreads();
+  for (int it = 0; it < nslab; ++it) {
+    const int cur = it & 1;
+    const bool more = it + 1 < nslab;
+    if (more) fetch(kbeg + (int64_t)(it + 1) * BK);
+    bf16x8 af[SA], bf[SB];
+#pragma unroll
+    for (int a = 0; a < SA; ++a) af[a] = *(const bf16x8*)&As[cur][wm * WM + 16 * a + li][8 * lk];
+#pragma unroll
+    for (int b = 0; b < SB; ++b) bf[b] = *(const bf16x8*)&Bs[cur][wn * WN + 16 * b + li][8 * lk];
+#pragma unroll
+    for (int a = 0; a < SA; ++a)
+#pragma unroll
+      for (int b = 0; b < SB; ++b)
+        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[b], af[a], acc[a][b], 0, 0, 0);
+    if (more) {
+      la.store_t(As[cur ^ 1], ra);
+      lb.store_t(Bs[cur ^ 1], rb);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < SA; ++a) {
+    const int64_t i = i0 + wm * WM + 16 * a + li;
+    const bool row_ok = i < g.M;
+    double cv[SB][4];
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = j0 + wn * WN + 16 * b + 4 * lk + r;
+        cv[b][r] = (row_ok && j < g.N && !g.P && g.beta != 0.0) ? g.C[i + j * g.ldc] : 0.0;
+      }
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = j0 + wn * WN + 16 * b + 4 * lk + r;
+        if (!row_ok || j >= g.N) continue;
+        const double v = g.alpha * (double)acc[a][b][r];
+        if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = v;
+        else g.C[i + j * g.ldc] = v + g.beta * cv[b][r];
+      }
+  }
+}
+
 __global__ void k_splitk_reduce(const double* P, int nsplit, int64_t M, int64_t N, double beta,
                                 double* C, int64_t ldc) {
   const int64_t MN = M * N;
@@ -264,10 +362,21 @@ static void launch_t(const GemmDesc& d, const GemmArgs& g, dim3 grid, hipStream_
     hipLaunchKernelGGL((k_gemm<BM, BN, true, true, CMP>), grid, dim3(256), 0, s, g);
 }
 
+template <int BM, int BN>
+static void launch_bf16(const GemmDesc& d, const GemmArgs& g, dim3 grid, hipStream_t s) {
+  if (d.ta == 'N' && d.tb == 'N')
+    hipLaunchKernelGGL((k_gemm_bf16<BM, BN, false, false>), grid, dim3(256), 0, s, g);
+  else if (d.ta == 'T' && d.tb == 'N')
+    hipLaunchKernelGGL((k_gemm_bf16<BM, BN, true, false>), grid, dim3(256), 0, s, g);
+  else if (d.ta == 'N' && d.tb == 'T')
+    hipLaunchKernelGGL((k_gemm_bf16<BM, BN, false, true>), grid, dim3(256), 0, s, g);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16<BM, BN, true, true>), grid, dim3(256), 0, s, g);
+}
+
 hipError_t gemm(const GemmDesc& d, hipStream_t s, double* scratch, int64_t scratch_doubles,
                 double* flops) {
   if (d.M <= 0 || d.N <= 0) return hipSuccess;
-  if (d.compute == COMPUTE_BF16) return hipErrorNotSupported;
   if (d.K <= 0) {
     // C = beta C: reuse the reduction kernel with zero partials is wasteful;
     // a K = 0 product only happens for empty panels, which callers avoid.
@@ -284,7 +393,7 @@ hipError_t gemm(const GemmDesc& d, hipStream_t s, double* scratch, int64_t scrat
     nsplit = std::max<int64_t>(nsplit, 1);
   }
   int64_t kchunk = (d.K + nsplit - 1) / nsplit;
-  kchunk = (kchunk + 15) / 16 * 16;
+  kchunk = (kchunk + 31) / 32 * 32;
   nsplit = (d.K + kchunk - 1) / kchunk;
   GemmArgs g{d.M, d.N, d.K, kchunk, d.alpha, d.beta, d.A, d.lda, d.B, d.ldb,
              d.C, d.ldc, nsplit > 1 ? scratch : nullptr, d.maskA, d.maskB};
@@ -292,9 +401,14 @@ hipError_t gemm(const GemmDesc& d, hipStream_t s, double* scratch, int64_t scrat
   const double gbytes = 8.0 * ((double)d.M * d.K + (double)d.K * d.N +
                                (d.beta == 0.0 ? 1.0 : 2.0) * (double)d.M * d.N);
   {
-    TimedLaunch tl(s, d.compute == COMPUTE_F32 ? "gemm_f32" : "gemm_f64", gbytes,
-                   2.0 * (double)d.M * d.N * d.K);
-    if (d.compute == COMPUTE_F32) {
+    TimedLaunch tl(s, d.compute == COMPUTE_F32    ? "gemm_f32"
+                      : d.compute == COMPUTE_BF16 ? "gemm_bf16"
+                                                  : "gemm_f64",
+                   gbytes, 2.0 * (double)d.M * d.N * d.K);
+    if (d.compute == COMPUTE_BF16) {
+      if (big) launch_bf16<128, 128>(d, g, grid, s);
+      else launch_bf16<64, 64>(d, g, grid, s);
+    } else if (d.compute == COMPUTE_F32) {
       if (big) launch_t<128, 128, COMPUTE_F32>(d, g, grid, s);
       else launch_t<64, 64, COMPUTE_F32>(d, g, grid, s);
     } else {

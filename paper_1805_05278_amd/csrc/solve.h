@@ -29,6 +29,12 @@ hipError_t solve_upper(hipStream_t s, int64_t n, int64_t nrhs, const double* R, 
 hipError_t solve_upper_trans(hipStream_t s, int64_t n, int64_t nrhs, const double* R,
                              int64_t ldr, double* X, int64_t ldx, double* scratch,
                              int64_t scratch_doubles);
+// Y[:, c] += sgn * a[c] * X[:, c] for c < ncols (a: device, one per column).
+void axpy_cols(hipStream_t s, int64_t rows, int64_t ncols, double sgn, const double* a,
+               const double* X, int64_t ldx, double* Y, int64_t ldy);
+// P[:, c] = S[:, c] + b[c] * P[:, c].
+void xpby_cols(hipStream_t s, int64_t rows, int64_t ncols, const double* S, int64_t lds,
+               const double* b, double* P, int64_t ldp);
 // out[j] = sum_i X[i, j]^2 for each of the n columns (fixed-order reduction).
 void column_sumsq(hipStream_t s, int64_t m, int64_t n, const double* X, int64_t ldx, double* out);
 

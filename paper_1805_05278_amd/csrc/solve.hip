@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_trsm_diag(int nb, int64_t nrhs, const d
     Rs[i][j] = (i < nb && j < nb) ? R[i + (int64_t)j * ldr] : 0.0;
   }
   __syncthreads();
-  for (int64_t c0 = 0; c0 < nrhs; c0 += 4) {
+  for (int64_t c0 = 4 * (int64_t)blockIdx.x; c0 < nrhs; c0 += 4 * (int64_t)gridDim.x) {
     const int64_t cc = c0 + col;
     const bool live = cc < nrhs && row < nb;
     double x = live ? X[row + cc * ldx] : 0.0;
@@ -133,6 +133,42 @@ __global__ __launch_bounds__(256) void k_column_sumsq(int64_t m, const double* X
   if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = s;
   __syncthreads();
   if (threadIdx.x == 0) out[j] = (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+static inline unsigned trsm_groups(int64_t nrhs) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((nrhs + 3) / 4, 4096));
+}
+
+__global__ void k_axpy_cols(int64_t rows, int64_t ncols, double sgn, const double* a,
+                            const double* X, int64_t ldx, double* Y, int64_t ldy) {
+  const int64_t total = rows * ncols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % rows, c = e / rows;
+    Y[i + c * ldy] += sgn * a[c] * X[i + c * ldx];
+  }
+}
+
+__global__ void k_xpby_cols(int64_t rows, int64_t ncols, const double* S, int64_t lds,
+                            const double* b, double* P, int64_t ldp) {
+  const int64_t total = rows * ncols;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e % rows, c = e / rows;
+    P[i + c * ldp] = S[i + c * lds] + b[c] * P[i + c * ldp];
+  }
+}
+
+void axpy_cols(hipStream_t s, int64_t rows, int64_t ncols, double sgn, const double* a,
+               const double* X, int64_t ldx, double* Y, int64_t ldy) {
+  hipLaunchKernelGGL(k_axpy_cols, dim3(nblocks_for(rows * ncols)), dim3(256), 0, s, rows, ncols,
+                     sgn, a, X, ldx, Y, ldy);
+}
+
+void xpby_cols(hipStream_t s, int64_t rows, int64_t ncols, const double* S, int64_t lds,
+               const double* b, double* P, int64_t ldp) {
+  hipLaunchKernelGGL(k_xpby_cols, dim3(nblocks_for(rows * ncols)), dim3(256), 0, s, rows, ncols,
+                     S, lds, b, P, ldp);
 }
 
 void zero_strict_lower(hipStream_t s, int64_t n, double* T, int64_t ldt) {
@@ -173,8 +209,8 @@ hipError_t solve_upper(hipStream_t s, int64_t n, int64_t nrhs, const double* R, 
     {
       TimedLaunch tl(s, "trsm_diag", 8.0 * (double)(i1 - i0) * (i1 - i0 + 2 * nrhs),
                      (double)(i1 - i0) * (i1 - i0) * nrhs);
-      hipLaunchKernelGGL(k_trsm_diag<false>, dim3(1), dim3(256), 0, s, (int)(i1 - i0), nrhs,
-                         R + i0 + i0 * ldr, ldr, X + i0, ldx);
+      hipLaunchKernelGGL(k_trsm_diag<false>, dim3(trsm_groups(nrhs)), dim3(256), 0, s,
+                         (int)(i1 - i0), nrhs, R + i0 + i0 * ldr, ldr, X + i0, ldx);
     }
     if (i0 > 0) {
       GemmDesc d;
@@ -207,8 +243,8 @@ hipError_t solve_upper_trans(hipStream_t s, int64_t n, int64_t nrhs, const doubl
     {
       TimedLaunch tl(s, "trsm_diag", 8.0 * (double)(i1 - i0) * (i1 - i0 + 2 * nrhs),
                      (double)(i1 - i0) * (i1 - i0) * nrhs);
-      hipLaunchKernelGGL(k_trsm_diag<true>, dim3(1), dim3(256), 0, s, (int)(i1 - i0), nrhs,
-                         R + i0 + i0 * ldr, ldr, X + i0, ldx);
+      hipLaunchKernelGGL(k_trsm_diag<true>, dim3(trsm_groups(nrhs)), dim3(256), 0, s,
+                         (int)(i1 - i0), nrhs, R + i0 + i0 * ldr, ldr, X + i0, ldx);
     }
     if (i1 < n) {
       GemmDesc d;
