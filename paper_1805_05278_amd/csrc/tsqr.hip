@@ -42,7 +42,7 @@ struct ChainQRArgs {
   double* X;       // leaf level: panel (in place); tree level: child R array
   int64_t ldx;
   int64_t xrows;   // leaf level: panel rows
-  int nblocks, chain_len, nbr, leaf;
+  int nblocks, chain_len, nbr;
   double* Y;       // tree levels: Y per node (kYS doubles, leading dim kYL)
   double* T;       // leaf: per block; tree: per node
   double* R;       // per chain / node
@@ -218,7 +218,8 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
   }
 }
 
-template <int H>
+// LEAF: the chain walks row blocks of the panel (else stacked child R's).
+template <int H, bool LEAF>
 __global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
   constexpr int RG = Lay<H>::RG, CPT = Lay<H>::CPT;
   const int t = threadIdx.x, rg = t % RG, cg = t / RG;
@@ -235,14 +236,14 @@ __global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
   for (int i = t; i < kTS; i += 512) {
     const int r = i % kNB, cc = i / kNB;
     double v = 0.0;
-    if (!a.leaf && r < nbr && cc < nbr) v = a.X[(int64_t)b0 * kTS + i];
+    if (!LEAF && r < nbr && cc < nbr) v = a.X[(int64_t)b0 * kTS + i];
     Rs[r][cc] = v;
     Gs[r][cc] = 0.0;
   }
   __syncthreads();
 
   double x[CPT][8];
-  if (a.leaf) {
+  if constexpr (LEAF) {
     for (int b = b0; b < b1; ++b) {
       const bool first = b == b0;
       const int64_t rstart = ((int64_t)b * a.xrows) / a.nblocks;
@@ -580,7 +581,7 @@ struct DownArgs {
   double* Q;           // leaf level, optional
   int64_t ldq;
   const double* LR;
-  int nblocks, chain_len, nbr, nq, leaf;
+  int nblocks, chain_len, nbr, nq;
 };
 
 // M = T B into Ms (T upper triangular from global, B in Bs); wave w computes
@@ -610,7 +611,7 @@ __device__ __forceinline__ void down_tb(const double* Tb, double (*Bs)[NQM + 4],
 
 // Rows of one leaf block (or one node's stacked children) receive
 // -Y M (+ B on the top rows of a leaf chain's first block).
-template <int RT, int NQM>
+template <int RT, int NQM, bool LEAF>
 __device__ __forceinline__ void down_emit(const DownArgs& a, double (*Bs)[NQM + 4],
                                           double (*Ms)[NQM + 4], const double* Yb, int64_t ldy,
                                           int rows, bool first, int64_t rstart, bool top_block,
@@ -654,7 +655,7 @@ __device__ __forceinline__ void down_emit(const DownArgs& a, double (*Bs)[NQM + 
           if (cc >= nq) continue;
           double v = -acc[s][g][r];
           if (first && row < nbr) v += Bs[row][cc];
-          if (a.leaf) {
+          if (LEAF) {
             if (cc < nbr) {
               if (top_block && row < nbr) v = a.LR[row + cc * kNB];
               a.A[rstart + row + (int64_t)cc * a.lda] = v;
@@ -670,8 +671,9 @@ __device__ __forceinline__ void down_emit(const DownArgs& a, double (*Bs)[NQM + 
   }
 }
 
-// RT: 16-row tiles per wave (block height 64 RT); NQM: max columns of B.
-template <int RT, int NQM>
+// RT: 16-row tiles per wave (block height 64 RT); NQM: max columns of B;
+// LEAF: emit the panel rows (else the children's B blocks).
+template <int RT, int NQM, bool LEAF>
 __global__ __launch_bounds__(256) void k_chain_down(DownArgs a) {
   constexpr int BLD = NQM + 4;
   __shared__ __align__(16) double Bs[kNB][BLD];
@@ -690,7 +692,7 @@ __global__ __launch_bounds__(256) void k_chain_down(DownArgs a) {
   }
   __syncthreads();
 
-  if (a.leaf) {
+  if constexpr (LEAF) {
     for (int b = b1 - 1; b >= b0; --b) {
       const bool first = b == b0;
       down_tb<NQM>(a.T + (int64_t)b * kTS, Bs, Ms, nbr, CT);
@@ -702,14 +704,14 @@ __global__ __launch_bounds__(256) void k_chain_down(DownArgs a) {
         }
       const int64_t rstart = ((int64_t)b * a.xrows) / a.nblocks;
       const int rows = (int)((((int64_t)b + 1) * a.xrows) / a.nblocks - rstart);
-      down_emit<RT, NQM>(a, Bs, Ms, a.A + rstart, a.lda, rows, first, rstart, b == 0, b0, CT);
+      down_emit<RT, NQM, true>(a, Bs, Ms, a.A + rstart, a.lda, rows, first, rstart, b == 0, b0, CT);
       __syncthreads();
     }
   } else {
     if (b1 - b0 >= 2) {
       down_tb<NQM>(a.T + (int64_t)chain * kTS, Bs, Ms, nbr, CT);
       __syncthreads();
-      down_emit<RT, NQM>(a, Bs, Ms, a.Y + (int64_t)chain * kYS, kYL, (b1 - b0 - 1) * nbr, false,
+      down_emit<RT, NQM, false>(a, Bs, Ms, a.Y + (int64_t)chain * kYS, kYL, (b1 - b0 - 1) * nbr, false,
                          0, false, b0, CT);
       __syncthreads();
     }
@@ -778,22 +780,22 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
   // Upsweep.
   {
     const TsqrLevel& l0 = p.levels[0];
-    ChainQRArgs a{P, ldp, p.rows, l0.nblocks, l0.chain_len, nbr, 1, nullptr, l0.T, l0.R};
+    ChainQRArgs a{P, ldp, p.rows, l0.nblocks, l0.chain_len, nbr, nullptr, l0.T, l0.R};
     // Read A, write V; write T per block and R per chain.  Flops: QR 2 m nb^2
     // plus the Gram products for T, m nb^2.
     TimedLaunch tl(s, "tsqr_chain_qr_leaf", 2.0 * pan + tri * (l0.nblocks + l0.nchains),
                    3.0 * (double)p.rows * nbr * nbr);
     if (p.leaf_rows == 256)
-      hipLaunchKernelGGL(k_chain_qr<256>, dim3(l0.nchains), dim3(512), 0, s, a);
+      hipLaunchKernelGGL((k_chain_qr<256, true>), dim3(l0.nchains), dim3(512), 0, s, a);
     else
-      hipLaunchKernelGGL(k_chain_qr<128>, dim3(l0.nchains), dim3(512), 0, s, a);
+      hipLaunchKernelGGL((k_chain_qr<128, true>), dim3(l0.nchains), dim3(512), 0, s, a);
   }
   for (int lev = 1; lev <= L; ++lev) {
     const TsqrLevel& lv = p.levels[lev];
-    ChainQRArgs a{p.levels[lev - 1].R, kNB, 0, lv.nblocks, lv.chain_len, nbr, 0, lv.Y, lv.T, lv.R};
+    ChainQRArgs a{p.levels[lev - 1].R, kNB, 0, lv.nblocks, lv.chain_len, nbr, lv.Y, lv.T, lv.R};
     TimedLaunch tl(s, "tsqr_chain_qr_tree", tri * (2.0 * lv.nblocks + 3.0 * lv.nchains),
                    3.0 * (double)lv.nblocks * nbr * nbr * nbr);
-    hipLaunchKernelGGL(k_chain_qr<kYL>, dim3(lv.nchains), dim3(512), 0, s, a);
+    hipLaunchKernelGGL((k_chain_qr<kYL, false>), dim3(lv.nchains), dim3(512), 0, s, a);
   }
   // Householder reconstruction at the root.
   const int nq = Q ? 2 * nbr : nbr;
@@ -831,13 +833,12 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     d.chain_len = lv.chain_len;
     d.nbr = nbr;
     d.nq = nq;
-    d.leaf = 0;
     TimedLaunch tl(s, "tsqr_down_tree", 8.0 * nbr * nq * 2.0 * lv.nblocks + tri * 2.0 * lv.nblocks,
                    3.0 * (double)lv.nblocks * nbr * nbr * nq);
     if (nq > kNB)
-      hipLaunchKernelGGL((k_chain_down<4, 128>), dim3(lv.nchains), dim3(256), 0, s, d);
+      hipLaunchKernelGGL((k_chain_down<4, 128, false>), dim3(lv.nchains), dim3(256), 0, s, d);
     else
-      hipLaunchKernelGGL((k_chain_down<4, 64>), dim3(lv.nchains), dim3(256), 0, s, d);
+      hipLaunchKernelGGL((k_chain_down<4, 64, false>), dim3(lv.nchains), dim3(256), 0, s, d);
   }
   {
     const TsqrLevel& l0 = p.levels[0];
@@ -854,21 +855,20 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     d.chain_len = l0.chain_len;
     d.nbr = nbr;
     d.nq = nq;
-    d.leaf = 1;
     // Read the basis, write V (and Q); T per block.  Flops: 2 m nb nq for
     // -Y M plus nb^2 nq per block for M = T B.
     TimedLaunch tl(s, "tsqr_down_leaf", pan * (Q ? 3.0 : 2.0) + tri * l0.nblocks,
                    2.0 * (double)p.rows * nbr * nq + (double)l0.nblocks * nbr * nbr * nq);
     if (p.leaf_rows == 256) {
       if (nq > kNB)
-        hipLaunchKernelGGL((k_chain_down<4, 128>), dim3(l0.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<4, 128, true>), dim3(l0.nchains), dim3(256), 0, s, d);
       else
-        hipLaunchKernelGGL((k_chain_down<4, 64>), dim3(l0.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<4, 64, true>), dim3(l0.nchains), dim3(256), 0, s, d);
     } else {
       if (nq > kNB)
-        hipLaunchKernelGGL((k_chain_down<2, 128>), dim3(l0.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<2, 128, true>), dim3(l0.nchains), dim3(256), 0, s, d);
       else
-        hipLaunchKernelGGL((k_chain_down<2, 64>), dim3(l0.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<2, 64, true>), dim3(l0.nchains), dim3(256), 0, s, d);
     }
   }
   return hipGetLastError();
