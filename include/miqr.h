@@ -186,6 +186,37 @@ miqr_status qr_solve_r(miqr_handle handle, void *stream, int64_t n,
                        int64_t nrhs, const double *VR, int64_t lda, double *X,
                        int64_t ldx);
 
+/* One problem of a batched least-squares call (device pointers). */
+typedef struct qr_batch_item {
+    int64_t m, n, nrhs; /* m >= n >= 1, 1 <= nrhs <= 8, n + nrhs <= 320 */
+    double *A;          /* m x n, lda >= m; overwritten (R in the upper n x n
+                           triangle, rows below it left as they were) */
+    int64_t lda;
+    double *B;          /* m x nrhs, ldb >= m; rows 0..n-1 receive X */
+    int64_t ldb;
+} qr_batch_item;
+
+/* Many independent least-squares problems in one persistent launch.  Each
+ * problem is solved by one workgroup: Householder QR of the augmented matrix
+ * [A | B] by a flat TSQR sweep over 64-row blocks (the TSQR of Sec. 5 /
+ * App. C.1 with a chain as its reduction tree; dlarfg sign rule), which leaves
+ * R and the top n rows of Q^T B, then back substitution.  Workgroups pop
+ * problems from a device queue, largest first.  A problem's arithmetic does
+ * not depend on the other problems in the call, so its result is bitwise the
+ * same alone and in any batch.
+ *   items (host array of `count`): problems; pointers must not overlap.
+ *   opts: NULL or precision MIQR_FP64 (the sweep has no GEMM for a lower
+ *   precision to speed up: MIQR_ENOTSUP otherwise).
+ *   status (host, `count` int32, may be NULL): when given, the call
+ *   synchronises the stream and writes 0, or j + 1 when R_jj == 0 exactly
+ *   (that problem's B then holds the top n rows of Q^T B and A is unchanged).
+ * Returns MIQR_ESINGULAR if status was given and some problem is singular.
+ * Errors: MIQR_EINVAL (a bad item; nothing is enqueued), MIQR_ENOMEM,
+ * MIQR_EHIP, MIQR_ENOTSUP. */
+miqr_status qr_lstsq_batched(miqr_handle handle, void *stream, int64_t count,
+                             const qr_batch_item *items, const qr_opts *opts,
+                             int32_t *status);
+
 #ifdef __cplusplus
 }
 #endif

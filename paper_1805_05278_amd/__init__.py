@@ -43,6 +43,11 @@ class QrInfo(ctypes.Structure):
                 ("backward_error", ctypes.c_double)]
 
 
+class QrBatchItem(ctypes.Structure):
+    _fields_ = [("m", _i64), ("n", _i64), ("nrhs", _i64), ("A", _vp), ("lda", _i64),
+                ("B", _vp), ("ldb", _i64)]
+
+
 _lib = None
 
 
@@ -78,6 +83,9 @@ def lib():
         L.qr_lstsq.restype = st
         L.qr_solve_r.argtypes = [_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64]
         L.qr_solve_r.restype = st
+        L.qr_lstsq_batched.argtypes = [_vp, _vp, _i64, ctypes.POINTER(QrBatchItem),
+                                       ctypes.POINTER(QrOpts), ctypes.POINTER(ctypes.c_int32)]
+        L.qr_lstsq_batched.restype = st
         L.miqr_last_gemm_flops.argtypes = [_vp]
         L.miqr_last_gemm_flops.restype = ctypes.c_double
         L.miqr_profile_enable.argtypes = [_vp, ctypes.c_int]
@@ -244,3 +252,23 @@ class Handle:
         out = Info(info.iterations, info.fallback, info.precision_used, info.singular_index,
                    info.backward_error) if want_info else None
         return st, out
+
+    def lstsq_batched(self, As, Bs, opts: Optional[QrOpts] = None, want_status: bool = True):
+        """Batched least squares in one launch: for each i, A_i is overwritten
+        (R in its upper triangle) and B_i[:n_i] receives the solution.  Returns
+        (status, per-problem statuses or None); raises on errors other than
+        ESINGULAR."""
+        if len(As) != len(Bs):
+            raise ValueError("As and Bs differ in length")
+        items = (QrBatchItem * max(len(As), 1))()
+        for i, (A, B) in enumerate(zip(As, Bs)):
+            ap, lda = _mat(A, "A")
+            bp, ldb = _mat(B, "B")
+            items[i] = QrBatchItem(A.shape[0], A.shape[1], B.shape[1], ap.value, lda, bp.value, ldb)
+        stat = (ctypes.c_int32 * max(len(As), 1))()
+        st = lib().qr_lstsq_batched(self._h, _stream(), len(As), items,
+                                    ctypes.byref(opts) if opts else None,
+                                    stat if want_status else None)
+        if st not in (OK, ESINGULAR):
+            self._check(st)
+        return st, (list(stat)[:len(As)] if want_status else None)

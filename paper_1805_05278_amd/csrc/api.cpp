@@ -9,6 +9,7 @@
 #include <string>
 #include <vector>
 
+#include "batched.h"
 #include "common.h"
 #include "gemm.h"
 #include "miqr.h"
@@ -28,6 +29,12 @@ struct miqr_ctx {
   bool profiling = false;
   KernelTimer timer;
   std::vector<std::string> prof_names;
+  // Pinned staging for batched task tables and statuses; table_ev marks the
+  // last upload out of it, so the next call may rewrite it.
+  BatchTask* pin_tasks = nullptr;
+  int32_t* pin_status = nullptr;
+  int64_t pin_cap = 0;
+  hipEvent_t table_ev = nullptr;
 };
 
 namespace {
@@ -558,6 +565,43 @@ miqr_status lstsq_fp64(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64
   return MIQR_OK;
 }
 
+// Pinned host staging for `count` tasks and statuses.  Waits for the previous
+// upload out of the staging buffer before it may be rewritten.
+miqr_status ensure_pinned(miqr_handle h, int64_t count) {
+  hipError_t e = hipSuccess;
+  if (!h->table_ev) {
+    e = hipEventCreateWithFlags(&h->table_ev, hipEventDisableTiming);
+    if (e != hipSuccess) return hip_fail(h, e, "hipEventCreate");
+  } else {
+    e = hipEventSynchronize(h->table_ev);
+    if (e != hipSuccess) return hip_fail(h, e, "hipEventSynchronize");
+  }
+  if (count <= h->pin_cap) return MIQR_OK;
+  if (h->pin_tasks) hipHostFree(h->pin_tasks);
+  if (h->pin_status) hipHostFree(h->pin_status);
+  h->pin_tasks = nullptr;
+  h->pin_status = nullptr;
+  h->pin_cap = 0;
+  const int64_t cap = std::max<int64_t>(count, 1024);
+  e = hipHostMalloc((void**)&h->pin_tasks, cap * sizeof(BatchTask), hipHostMallocDefault);
+  if (e == hipSuccess)
+    e = hipHostMalloc((void**)&h->pin_status, cap * sizeof(int32_t), hipHostMallocDefault);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(h, MIQR_ENOMEM, "pinned staging allocation failed");
+  }
+  h->pin_cap = cap;
+  return MIQR_OK;
+}
+
+// Algorithmic bytes and flops of one batched problem (read [A | B], write R
+// into A and X into B; Householder QR of A plus Q^T B and back substitution).
+void batch_item_cost(const qr_batch_item& it, double* bytes, double* flops) {
+  const double m = (double)it.m, n = (double)it.n, k = (double)it.nrhs;
+  *bytes += 8.0 * (m * (n + k) + n * (n + 1) / 2 + n * k);
+  *flops += 2.0 * m * n * n - 2.0 * n * n * n / 3.0 + 4.0 * m * n * k + n * n * k;
+}
+
 }  // namespace
 
 extern "C" {
@@ -587,6 +631,9 @@ miqr_status miqr_destroy(miqr_handle h) {
   hipDeviceSynchronize();
   if (h->ws) hipFree(h->ws);
   if (h->dflag) hipFree(h->dflag);
+  if (h->pin_tasks) hipHostFree(h->pin_tasks);
+  if (h->pin_status) hipHostFree(h->pin_status);
+  if (h->table_ev) hipEventDestroy(h->table_ev);
   delete h;
   return MIQR_OK;
 }
@@ -849,6 +896,97 @@ miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t 
     }
     info->backward_error = worst;
   }
+  return MIQR_OK;
+}
+
+miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
+                             const qr_batch_item* items, const qr_opts* o, int32_t* status) {
+  if (!h) return MIQR_EINVAL;
+  ProfScope prof_scope(h);
+  h->err.clear();
+  if (count < 0 || count > (int64_t)1 << 30 || (count > 0 && !items))
+    return fail(h, MIQR_EINVAL, "bad count or items");
+  if (o && o->precision != MIQR_FP64)
+    return fail(h, MIQR_ENOTSUP, "batched least squares runs in FP64 only");
+  if (o && (o->normalize || o->Q)) return fail(h, MIQR_ENOTSUP, "batched lstsq takes no Q/normalize");
+  int64_t rtot = 0;
+  double bytes = 0.0, flops = 0.0;
+  for (int64_t i = 0; i < count; ++i) {
+    const qr_batch_item& it = items[i];
+    const std::string at = " (item " + std::to_string(i) + ")";
+    if (it.n < 1 || it.m < it.n || it.m > INT32_MAX)
+      return fail(h, MIQR_EINVAL, "need 2^31 > m >= n >= 1" + at);
+    if (it.nrhs < 1 || it.nrhs > kBatchMaxRhs)
+      return fail(h, MIQR_EINVAL, "need 1 <= nrhs <= " + std::to_string(kBatchMaxRhs) + at);
+    if (it.n + it.nrhs > kBatchThreads)
+      return fail(h, MIQR_EINVAL, "need n + nrhs <= " + std::to_string(kBatchThreads) + at);
+    if (it.lda < it.m || it.ldb < it.m) return fail(h, MIQR_EINVAL, "leading dimension too small" + at);
+    if (bad_ptr(it.A) || bad_ptr(it.B)) return fail(h, MIQR_EINVAL, "null pointer" + at);
+    rtot += (it.n * (it.n + it.nrhs) + 31) & ~int64_t(31);
+    batch_item_cost(it, &bytes, &flops);
+  }
+  if (count == 0) return MIQR_OK;
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
+  hipStream_t s = (hipStream_t)stream;
+  const int64_t task_d = (count * (int64_t)sizeof(BatchTask) + 255) / 256 * 32;
+  const int64_t stat_d = (count * 4 + 255) / 256 * 32;
+  miqr_status st = ensure_ws(h, (size_t)(task_d + stat_d + 32 + rtot) * sizeof(double));
+  if (st != MIQR_OK) return st;
+  st = ensure_pinned(h, count);
+  if (st != MIQR_OK) return st;
+  Arena ar{(double*)h->ws};
+  BatchTask* dtasks = (BatchTask*)ar.take(task_d);
+  int* dstatus = (int*)ar.take(stat_d);
+  int* counter = (int*)ar.take(32);
+  double* rbase = ar.take(rtot);
+  // Largest problems first (their cost is about blocks x columns steps), so
+  // the persistent grid ends with small problems and finishes evenly.
+  std::vector<int64_t> order((size_t)count);
+  for (int64_t i = 0; i < count; ++i) order[(size_t)i] = i;
+  auto cost = [&](int64_t i) {
+    return ((items[i].m + kBatchRows - 1) / kBatchRows + 1) * items[i].n;
+  };
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int64_t a, int64_t b) { return cost(a) > cost(b); });
+  int64_t roff = 0;
+  for (int64_t k = 0; k < count; ++k) {
+    const int64_t i = order[(size_t)k];
+    const qr_batch_item& it = items[i];
+    BatchTask t{};
+    t.A = it.A;
+    t.B = it.B;
+    t.R = rbase + roff;
+    t.tau = nullptr;
+    t.lda = it.lda;
+    t.ldb = it.ldb;
+    t.m = (int)it.m;
+    t.n = (int)it.n;
+    t.nrhs = (int)it.nrhs;
+    t.flags = kTaskWriteR;
+    t.slot = (int)i;
+    roff += (it.n * (it.n + it.nrhs) + 31) & ~int64_t(31);
+    h->pin_tasks[k] = t;
+  }
+  hipError_t e = hipMemcpyAsync(dtasks, h->pin_tasks, count * sizeof(BatchTask),
+                                hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(h->table_ev, s);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched upload");
+  batched_ls(s, dtasks, (int)count, counter, dstatus, batched_grid(h->device, (int)count), bytes,
+             flops);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched launch");
+  if (!status) return MIQR_OK;
+  e = hipMemcpyAsync(h->pin_status, dstatus, count * sizeof(int32_t), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched status");
+  int64_t bad = -1;
+  for (int64_t i = 0; i < count; ++i) {
+    status[i] = h->pin_status[i];
+    if (status[i] != 0 && bad < 0) bad = i;
+  }
+  if (bad >= 0)
+    return fail(h, MIQR_ESINGULAR, "item " + std::to_string(bad) + ": R(" +
+                                       std::to_string(status[bad] - 1) + ") == 0");
   return MIQR_OK;
 }
 

@@ -1,0 +1,264 @@
+// Batched least squares: one workgroup per problem, popped from a device queue
+// by a persistent grid.
+//
+// A problem min ||B - A X|| (m x n, nrhs right-hand sides) is solved by
+// Householder QR of the augmented matrix [A | B] with a flat TSQR sweep (the
+// paper's TSQR with a chain as its tree, Sec. 5 / App. C.1): the running R
+// (n x (n + nrhs), zero at the start) is stacked over each 64-row block X of
+// [A | B] in turn, and [R; X] is reduced column by column.  The reflector of
+// column j is v = [e_j; y] (R is upper triangular, so v has a single entry in
+// the R part), with the dlarfg sign rule.  After the last block R holds the R
+// factor of A and, in its last nrhs columns, the top n rows of Q^T B; back
+// substitution gives X.
+//
+// Thread c owns column c of [A | B]: the block's 64 entries in registers and
+// column c of R in global memory, which no other thread touches.  A step is
+// one reflector: the pivot thread builds y and tau and posts them in LDS; every
+// thread to its right forms its dot product with y locally (no cross-thread
+// reduction) and updates its column.  One barrier per step.
+#include <climits>
+
+#include "batched.h"
+#include "profiler.h"
+
+namespace miqr {
+namespace {
+
+constexpr int H = kBatchRows;
+
+__global__ void k_batch_reset(int* counter) {
+  if (threadIdx.x == 0) counter[0] = 0;
+}
+
+// Flat TSQR sweep of one problem (flags without kTaskApply).
+__device__ void batch_factor(const BatchTask& t, double (*ybuf)[H], double* tbuf) {
+  const int c = threadIdx.x;
+  const int n = t.n, N = n + t.nrhs, m = t.m;
+  const bool own = c < N;
+  const bool keep = (t.flags & kTaskKeep) != 0;
+  double* col = nullptr;
+  if (own) col = c < n ? t.A + (int64_t)c * t.lda : t.B + (int64_t)(c - n) * t.ldb;
+  double* Rc = t.R + (int64_t)c * n;
+  const int jmax = c < n ? c : n - 1;  // last row of R in column c
+  if (own)
+    for (int j = 0; j <= jmax; ++j) Rc[j] = 0.0;
+  const int nblk = (m + H - 1) / H;
+  double x[H];
+  for (int bk = 0; bk < nblk; ++bk) {
+    const int r0 = bk * H;
+    const int rows = min(H, m - r0);
+    if (own) {
+      if (rows == H) {
+#pragma unroll
+        for (int r = 0; r < H; ++r) x[r] = col[r0 + r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < H; ++r) x[r] = r < rows ? col[r0 + r] : 0.0;
+      }
+    }
+    double rnext = own ? Rc[0] : 0.0;
+    for (int j = 0; j < n; ++j) {
+      const int slot = j & 1;
+      const double rj = rnext;  // R[j, c]
+      if (own && j + 1 <= jmax) rnext = Rc[j + 1];
+      if (c == j) {
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+        for (int r = 0; r < H; r += 4) {
+          s0 += x[r] * x[r];
+          s1 += x[r + 1] * x[r + 1];
+          s2 += x[r + 2] * x[r + 2];
+          s3 += x[r + 3] * x[r + 3];
+        }
+        const double sig2 = (s0 + s1) + (s2 + s3);
+        const double alpha = rj;
+        double tau = 0.0, beta = alpha;
+        if (sig2 != 0.0) {
+          const double nrm = sqrt(alpha * alpha + sig2);
+          beta = alpha >= 0.0 ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+          const double sc = 1.0 / (alpha - beta);
+#pragma unroll
+          for (int r = 0; r < H; ++r) x[r] *= sc;
+        }
+        Rc[j] = beta;
+#pragma unroll
+        for (int r = 0; r < H; ++r) ybuf[slot][r] = x[r];
+        tbuf[slot] = tau;
+        if (keep) t.tau[(int64_t)bk * n + j] = tau;
+      }
+      __syncthreads();
+      if (own && c > j) {
+        const double tau = tbuf[slot];
+        if (tau != 0.0) {
+          const double* y = ybuf[slot];
+          double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
+#pragma unroll
+          for (int r = 0; r < H; r += 4) {
+            d0 += y[r] * x[r];
+            d1 += y[r + 1] * x[r + 1];
+            d2 += y[r + 2] * x[r + 2];
+            d3 += y[r + 3] * x[r + 3];
+          }
+          const double tw = tau * (rj + ((d0 + d1) + (d2 + d3)));
+          Rc[j] = rj - tw;
+          // Read y from LDS again rather than holding all 64 values live
+          // across both passes (keeps the kernel at three waves per SIMD).
+          asm volatile("" ::: "memory");
+#pragma unroll
+          for (int r = 0; r < H; ++r) x[r] -= tw * y[r];
+        }
+      }
+    }
+    if (keep && c < n) {
+      if (rows == H) {
+#pragma unroll
+        for (int r = 0; r < H; ++r) col[r0 + r] = x[r];
+      } else {
+#pragma unroll
+        for (int r = 0; r < H; ++r)
+          if (r < rows) col[r0 + r] = x[r];
+      }
+    }
+  }
+}
+
+// Replay stored reflectors on B only (kTaskApply).  Wave k (< nrhs) carries
+// right-hand side k with lane r holding row r of the block; a step is a
+// wave-wide dot product (DPP/shuffle sum), no workgroup barrier.
+__device__ void batch_apply(const BatchTask& t, double (*cbuf)[kBatchThreads]) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int n = t.n, m = t.m;
+  const int nblk = (m + H - 1) / H;
+  double* cb = cbuf[w];  // running top n rows of Q^T b for this wave's column
+  for (int k = w; k < t.nrhs; k += kBatchThreads / 64) {
+    double* b = t.B + (int64_t)k * t.ldb;
+    for (int j = l; j < n; j += 64) cb[j] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    for (int bk = 0; bk < nblk; ++bk) {
+      const int r0 = bk * H;
+      const bool in = r0 + l < m;
+      double br = in ? b[r0 + l] : 0.0;
+      const double* Y = t.A + r0 + l;
+      const double* tb = t.tau + (int64_t)bk * n;
+      double ynext = in ? Y[0] : 0.0;
+      for (int j = 0; j < n; ++j) {
+        const double y = ynext;
+        if (j + 1 < n) ynext = in ? Y[(int64_t)(j + 1) * t.lda] : 0.0;
+        const double tau = tb[j];
+        if (tau == 0.0) continue;
+        double d = y * br;
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o);
+        const double rj = cb[j];
+        const double tw = tau * (rj + d);
+        br -= tw * y;
+        __builtin_amdgcn_wave_barrier();
+        if (l == 0) cb[j] = rj - tw;
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    double* Rk = t.R + (int64_t)(n + k) * n;
+    for (int j = l; j < n; j += 64) Rk[j] = cb[j];
+    __builtin_amdgcn_wave_barrier();
+  }
+}
+
+// R x = c for the nrhs right-hand sides in R's last columns; thread l owns row
+// l.  Returns the 1-based index of the first zero diagonal entry (0 if none);
+// then B's top rows receive c unchanged.
+__device__ int batch_solve(const BatchTask& t, double (*xbuf)[kBatchMaxRhs], int* s_sing) {
+  const int l = threadIdx.x;
+  const int n = t.n, nrhs = t.nrhs;
+  const double* R = t.R;
+  if (l == 0) *s_sing = INT_MAX;
+  __syncthreads();
+  if (l < n && R[l + (int64_t)l * n] == 0.0) atomicMin(s_sing, l);
+  __syncthreads();
+  const int sing = *s_sing;
+  double cv[kBatchMaxRhs];
+#pragma unroll
+  for (int k = 0; k < kBatchMaxRhs; ++k)
+    cv[k] = (k < nrhs && l < n) ? R[l + (int64_t)(n + k) * n] : 0.0;
+  if (sing == INT_MAX) {
+    double rl = l < n ? R[l + (int64_t)(n - 1) * n] : 0.0;  // R[l, n-1]
+    for (int i = n - 1; i >= 0; --i) {
+      const int slot = i & 1;
+      const double rcur = rl;
+      if (i >= 1 && l <= i - 1) rl = R[l + (int64_t)(i - 1) * n];
+      if (l == i) {
+#pragma unroll
+        for (int k = 0; k < kBatchMaxRhs; ++k) {
+          cv[k] = cv[k] / rcur;
+          xbuf[slot][k] = cv[k];
+        }
+      }
+      __syncthreads();
+      if (l < i) {
+#pragma unroll
+        for (int k = 0; k < kBatchMaxRhs; ++k) cv[k] -= rcur * xbuf[slot][k];
+      }
+    }
+  }
+  if (l < n)
+    for (int k = 0; k < nrhs; ++k) t.B[l + (int64_t)k * t.ldb] = cv[k];
+  return sing == INT_MAX ? 0 : sing + 1;
+}
+
+__global__ __launch_bounds__(kBatchThreads, 3) void k_batched_ls(const BatchTask* tasks, int count,
+                                                              int* counter, int* status) {
+  __shared__ __align__(16) double ybuf[2][H];
+  __shared__ double tbuf[2];
+  __shared__ double xbuf[2][kBatchMaxRhs];
+  __shared__ double cbuf[kBatchThreads / 64][kBatchThreads];
+  __shared__ int s_idx, s_sing;
+  for (;;) {
+    if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
+    __syncthreads();
+    // Uniform across the workgroup: keeps the task's fields in scalar registers.
+    const int idx = __builtin_amdgcn_readfirstlane(s_idx);
+    __syncthreads();
+    if (idx >= count) break;
+    const BatchTask t = tasks[idx];
+    if (t.flags & kTaskApply) {
+      batch_apply(t, cbuf);
+    } else {
+      batch_factor(t, ybuf, tbuf);
+    }
+    __syncthreads();
+    const int st = batch_solve(t, xbuf, &s_sing);
+    if ((t.flags & kTaskWriteR) && st == 0) {
+      const int c = threadIdx.x;
+      if (c < t.n)
+        for (int j = 0; j <= c; ++j) t.A[j + (int64_t)c * t.lda] = t.R[j + (int64_t)c * t.n];
+    }
+    if (threadIdx.x == 0) status[t.slot] = st;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+int batched_grid(int device, int count) {
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    cus = 256;
+  int per = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched_ls, kBatchThreads, 0) !=
+          hipSuccess ||
+      per < 1)
+    per = 1;
+  const long long g = (long long)cus * per;
+  return (int)(count < g ? count : g);
+}
+
+void batched_ls(hipStream_t s, const BatchTask* tasks, int count, int* counter, int* status,
+                int grid, double bytes, double flops) {
+  if (count <= 0 || grid <= 0) return;
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counter);
+  TimedLaunch tl(s, "batched_ls", bytes, flops);
+  hipLaunchKernelGGL(k_batched_ls, dim3(grid), dim3(kBatchThreads), 0, s, tasks, count, counter,
+                     status);
+}
+
+}  // namespace miqr

@@ -114,3 +114,13 @@ def serving_trace(n_requests: int, qps: float, seed: int,
         k = int(r.integers(nrhs_range[0], nrhs_range[1] + 1))
         out.append(Request(i, t, m, n, k, seed * 1_000_003 + i))
     return out
+
+
+def gaussian_device(m: int, n: int, seed: int, device="cuda"):
+    """m x n column-major float64 torch tensor of N(0, 1) entries drawn on the
+    device from torch's seeded generator (for batches too large to draw on the
+    host); copy it to the host to hand the same values to the oracle."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return torch.randn((n, m), generator=g, dtype=torch.float64, device=device).t()
