@@ -217,6 +217,78 @@ miqr_status qr_lstsq_batched(miqr_handle handle, void *stream, int64_t count,
                              const qr_batch_item *items, const qr_opts *opts,
                              int32_t *status);
 
+/* ---- Serving loop -------------------------------------------------------
+ * A least-squares server on one device.  Requests (host matrices) wait in
+ * arrival order until device memory for them fits in the HBM budget; then
+ * their upload starts on a copy stream.  Uploaded requests are packed into
+ * batches solved by the batched kernel of qr_lstsq_batched, one captured-graph
+ * replay per batch, with up to two batches in flight: requests that arrive
+ * while a batch runs join the next one (continuous batching), and their
+ * uploads overlap the running batch.  A request's result is bitwise the same
+ * whatever it is batched with.  The caller drives the server with
+ * qr_server_poll; the server is not thread-safe.  Host buffers passed to
+ * submit/resolve must stay valid and unchanged until the request is reported
+ * done; pinned host memory lets uploads overlap compute. */
+typedef struct miqr_server *miqr_server_handle;
+
+typedef struct qr_server_opts {
+    int64_t hbm_budget;   /* device bytes for admitted requests (0: 8 GiB) */
+    int64_t max_batch;    /* requests per launch (0: 4096) */
+    int64_t max_pending;  /* waiting requests before submit says MIQR_EBUSY
+                             (0: 2^20) */
+    int64_t stage_bytes;  /* per in-flight batch, solution staging (0: 64 MiB) */
+    int32_t keep_factors; /* nonzero: each factorisation stays on the device
+                             for qr_server_resolve until qr_server_release */
+    int32_t pad;
+} qr_server_opts;
+
+typedef struct qr_server_done {
+    int64_t id;
+    int32_t status;     /* 0, or j + 1 if R_jj == 0 (X then holds the top n
+                           rows of Q^T B) */
+    int32_t batch_size; /* requests in the launch that served it */
+    double submit_s;    /* server clock, seconds: submission */
+    double start_s;     /* launch of its batch */
+    double end_s;       /* completion observed by qr_server_poll */
+} qr_server_done;
+
+/* Create a server on the handle's device (allocates the HBM budget, two batch
+ * slots and their captured graphs).  The handle must outlive the server. */
+miqr_status qr_server_create(miqr_handle handle, const qr_server_opts *opts,
+                             miqr_server_handle *server);
+/* Wait for in-flight work and free everything the server holds. */
+miqr_status qr_server_destroy(miqr_server_handle server);
+/* Seconds on the server's clock (the clock of qr_server_done). */
+double qr_server_clock(miqr_server_handle server);
+/* Queue min ||B - A X||: A (host, m x n, lda), B (host, m x nrhs, ldb); X
+ * (host, n x nrhs, ldx) receives the solution.  Limits as qr_batch_item.
+ * MIQR_EBUSY when max_pending requests are already waiting; MIQR_EINVAL for a
+ * request that cannot fit the budget even alone. */
+miqr_status qr_server_submit(miqr_server_handle server, int64_t m, int64_t n,
+                             int64_t nrhs, const double *A, int64_t lda,
+                             const double *B, int64_t ldb, double *X,
+                             int64_t ldx, int64_t *id);
+/* Queue further right-hand sides against a finished request whose
+ * factorisation was kept (keep_factors): only B is uploaded; the stored
+ * reflectors are replayed on it, then back substitution. */
+miqr_status qr_server_resolve(miqr_server_handle server, int64_t factored_id,
+                              int64_t nrhs, const double *B, int64_t ldb,
+                              double *X, int64_t ldx, int64_t *id);
+/* Drop a kept factorisation (MIQR_EBUSY while solves against it run). */
+miqr_status qr_server_release(miqr_server_handle server, int64_t factored_id);
+/* Retire finished batches (copying solutions into the callers' X), admit
+ * waiting requests, launch batches into free slots, then report up to
+ * `capacity` finished requests.  wait != 0 blocks until at least one request
+ * is finished, unless nothing is queued or in flight. */
+miqr_status qr_server_poll(miqr_server_handle server, int wait,
+                           qr_server_done *done, int64_t capacity,
+                           int64_t *ndone);
+/* Requests waiting, uploaded but not launched, and running; device bytes in
+ * use.  Any pointer may be NULL. */
+miqr_status qr_server_stats(miqr_server_handle server, int64_t *pending,
+                            int64_t *admitted, int64_t *running,
+                            int64_t *hbm_used);
+
 #ifdef __cplusplus
 }
 #endif

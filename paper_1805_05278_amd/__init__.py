@@ -48,6 +48,17 @@ class QrBatchItem(ctypes.Structure):
                 ("B", _vp), ("ldb", _i64)]
 
 
+class ServerOpts(ctypes.Structure):
+    _fields_ = [("hbm_budget", _i64), ("max_batch", _i64), ("max_pending", _i64),
+                ("stage_bytes", _i64), ("keep_factors", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class ServerDone(ctypes.Structure):
+    _fields_ = [("id", _i64), ("status", ctypes.c_int32), ("batch_size", ctypes.c_int32),
+                ("submit_s", ctypes.c_double), ("start_s", ctypes.c_double),
+                ("end_s", ctypes.c_double)]
+
+
 _lib = None
 
 
@@ -86,6 +97,25 @@ def lib():
         L.qr_lstsq_batched.argtypes = [_vp, _vp, _i64, ctypes.POINTER(QrBatchItem),
                                        ctypes.POINTER(QrOpts), ctypes.POINTER(ctypes.c_int32)]
         L.qr_lstsq_batched.restype = st
+        L.qr_server_create.argtypes = [_vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
+        L.qr_server_create.restype = st
+        L.qr_server_destroy.argtypes = [_vp]
+        L.qr_server_destroy.restype = st
+        L.qr_server_clock.argtypes = [_vp]
+        L.qr_server_clock.restype = ctypes.c_double
+        L.qr_server_submit.argtypes = [_vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp, _i64,
+                                       ctypes.POINTER(_i64)]
+        L.qr_server_submit.restype = st
+        L.qr_server_resolve.argtypes = [_vp, _i64, _i64, _vp, _i64, _vp, _i64,
+                                        ctypes.POINTER(_i64)]
+        L.qr_server_resolve.restype = st
+        L.qr_server_release.argtypes = [_vp, _i64]
+        L.qr_server_release.restype = st
+        L.qr_server_poll.argtypes = [_vp, ctypes.c_int, ctypes.POINTER(ServerDone), _i64,
+                                     ctypes.POINTER(_i64)]
+        L.qr_server_poll.restype = st
+        L.qr_server_stats.argtypes = [_vp] + [ctypes.POINTER(_i64)] * 4
+        L.qr_server_stats.restype = st
         L.miqr_last_gemm_flops.argtypes = [_vp]
         L.miqr_last_gemm_flops.restype = ctypes.c_double
         L.miqr_profile_enable.argtypes = [_vp, ctypes.c_int]
@@ -272,3 +302,99 @@ class Handle:
         if st not in (OK, ESINGULAR):
             self._check(st)
         return st, (list(stat)[:len(As)] if want_status else None)
+
+
+def _host(x, name: str):
+    """(pointer, leading dimension) of a host column-major float64 matrix: a
+    Fortran-ordered numpy array (or a view with unit row stride), or a CPU torch
+    tensor with stride(0) == 1 (pin it for overlapped uploads)."""
+    import numpy as np
+    try:
+        import torch
+    except ImportError:  # pragma: no cover
+        torch = None
+    if torch is not None and isinstance(x, torch.Tensor):
+        if x.is_cuda or x.dtype != torch.float64 or x.dim() != 2:
+            raise TypeError("%s must be a 2-D float64 CPU tensor" % name)
+        if x.shape[0] > 1 and x.stride(0) != 1:
+            raise ValueError("%s must be column-major" % name)
+        return x.data_ptr(), max(x.stride(1), x.shape[0], 1)
+    if not isinstance(x, np.ndarray) or x.dtype != np.float64 or x.ndim != 2:
+        raise TypeError("%s must be a 2-D float64 numpy array" % name)
+    if x.shape[0] > 1 and x.strides[0] != 8:
+        raise ValueError("%s must be column-major (Fortran order)" % name)
+    ld = x.strides[1] // 8 if x.shape[1] > 1 else x.shape[0]
+    return x.ctypes.data, max(ld, x.shape[0], 1)
+
+
+class Server:
+    """Least-squares server on the handle's device (include/miqr.h: serving
+    loop).  Host inputs are referenced until their request is reported done."""
+
+    def __init__(self, handle: Handle, hbm_budget=0, max_batch=0, max_pending=0,
+                 stage_bytes=0, keep_factors=False):
+        self._handle = handle
+        o = ServerOpts(hbm_budget, max_batch, max_pending, stage_bytes,
+                       1 if keep_factors else 0, 0)
+        self._s = _vp()
+        handle._check(lib().qr_server_create(handle._h, ctypes.byref(o), ctypes.byref(self._s)))
+        self._hold = {}
+        self._buf = (ServerDone * 4096)()
+
+    def close(self):
+        if self._s:
+            lib().qr_server_destroy(self._s)
+            self._s = _vp()
+            self._hold.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def clock(self) -> float:
+        return float(lib().qr_server_clock(self._s))
+
+    def submit(self, A, B, X) -> int:
+        """Queue min ||B - A X||; X (n x nrhs host) receives the solution."""
+        ap, lda = _host(A, "A")
+        bp, ldb = _host(B, "B")
+        xp, ldx = _host(X, "X")
+        rid = _i64()
+        self._handle._check(lib().qr_server_submit(self._s, A.shape[0], A.shape[1], B.shape[1],
+                                                   ap, lda, bp, ldb, xp, ldx, ctypes.byref(rid)))
+        self._hold[rid.value] = (A, B, X)
+        return rid.value
+
+    def resolve(self, factored_id: int, B, X) -> int:
+        bp, ldb = _host(B, "B")
+        xp, ldx = _host(X, "X")
+        rid = _i64()
+        self._handle._check(lib().qr_server_resolve(self._s, factored_id, B.shape[1], bp, ldb,
+                                                    xp, ldx, ctypes.byref(rid)))
+        self._hold[rid.value] = (B, X)
+        return rid.value
+
+    def release(self, factored_id: int):
+        self._handle._check(lib().qr_server_release(self._s, factored_id))
+
+    def poll(self, wait: bool = False):
+        """List of finished requests: dicts with id, status, batch_size and the
+        submit/start/end times (server clock, seconds)."""
+        n = _i64()
+        self._handle._check(lib().qr_server_poll(self._s, 1 if wait else 0, self._buf,
+                                                 len(self._buf), ctypes.byref(n)))
+        out = []
+        for i in range(n.value):
+            d = self._buf[i]
+            self._hold.pop(d.id, None)
+            out.append(dict(id=d.id, status=d.status, batch_size=d.batch_size,
+                            submit_s=d.submit_s, start_s=d.start_s, end_s=d.end_s))
+        return out
+
+    def stats(self) -> dict:
+        v = [_i64() for _ in range(4)]
+        self._handle._check(lib().qr_server_stats(self._s, *[ctypes.byref(x) for x in v]))
+        return dict(pending=v[0].value, admitted=v[1].value, running=v[2].value,
+                    hbm_used=v[3].value)

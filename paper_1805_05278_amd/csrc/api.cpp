@@ -12,6 +12,7 @@
 #include "batched.h"
 #include "common.h"
 #include "gemm.h"
+#include "handle.h"
 #include "miqr.h"
 #include "profiler.h"
 #include "solve.h"
@@ -19,23 +20,7 @@
 
 using namespace miqr;
 
-struct miqr_ctx {
-  int device = 0;
-  char* ws = nullptr;
-  size_t ws_bytes = 0;
-  int* dflag = nullptr;
-  std::string err;
-  double gemm_flops = 0.0;  // multiply-add flops of the GEMMs launched by the last call
-  bool profiling = false;
-  KernelTimer timer;
-  std::vector<std::string> prof_names;
-  // Pinned staging for batched task tables and statuses; table_ev marks the
-  // last upload out of it, so the next call may rewrite it.
-  BatchTask* pin_tasks = nullptr;
-  int32_t* pin_status = nullptr;
-  int64_t pin_cap = 0;
-  hipEvent_t table_ev = nullptr;
-};
+
 
 namespace {
 // Points the launch-site timer at the handle for the duration of an entry point.
@@ -583,7 +568,7 @@ miqr_status ensure_pinned(miqr_handle h, int64_t count) {
   h->pin_status = nullptr;
   h->pin_cap = 0;
   const int64_t cap = std::max<int64_t>(count, 1024);
-  e = hipHostMalloc((void**)&h->pin_tasks, cap * sizeof(BatchTask), hipHostMallocDefault);
+  e = hipHostMalloc((void**)&h->pin_tasks, batch_table_bytes(cap), hipHostMallocDefault);
   if (e == hipSuccess)
     e = hipHostMalloc((void**)&h->pin_status, cap * sizeof(int32_t), hipHostMallocDefault);
   if (e != hipSuccess) {
@@ -909,7 +894,7 @@ miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
   if (o && o->precision != MIQR_FP64)
     return fail(h, MIQR_ENOTSUP, "batched least squares runs in FP64 only");
   if (o && (o->normalize || o->Q)) return fail(h, MIQR_ENOTSUP, "batched lstsq takes no Q/normalize");
-  int64_t rtot = 0;
+  int64_t rtot = 0;  // R (n x n) and C (n x nrhs) per problem, each 32-double aligned
   double bytes = 0.0, flops = 0.0;
   for (int64_t i = 0; i < count; ++i) {
     const qr_batch_item& it = items[i];
@@ -922,20 +907,20 @@ miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
       return fail(h, MIQR_EINVAL, "need n + nrhs <= " + std::to_string(kBatchThreads) + at);
     if (it.lda < it.m || it.ldb < it.m) return fail(h, MIQR_EINVAL, "leading dimension too small" + at);
     if (bad_ptr(it.A) || bad_ptr(it.B)) return fail(h, MIQR_EINVAL, "null pointer" + at);
-    rtot += (it.n * (it.n + it.nrhs) + 31) & ~int64_t(31);
+    rtot += ((it.n * it.n + 31) & ~int64_t(31)) + ((it.n * it.nrhs + 31) & ~int64_t(31));
     batch_item_cost(it, &bytes, &flops);
   }
   if (count == 0) return MIQR_OK;
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
-  const int64_t task_d = (count * (int64_t)sizeof(BatchTask) + 255) / 256 * 32;
+  const int64_t task_d = ((int64_t)batch_table_bytes(count) + 255) / 256 * 32;
   const int64_t stat_d = (count * 4 + 255) / 256 * 32;
   miqr_status st = ensure_ws(h, (size_t)(task_d + stat_d + 32 + rtot) * sizeof(double));
   if (st != MIQR_OK) return st;
   st = ensure_pinned(h, count);
   if (st != MIQR_OK) return st;
   Arena ar{(double*)h->ws};
-  BatchTask* dtasks = (BatchTask*)ar.take(task_d);
+  BatchHeader* dtable = (BatchHeader*)ar.take(task_d);
   int* dstatus = (int*)ar.take(stat_d);
   int* counter = (int*)ar.take(32);
   double* rbase = ar.take(rtot);
@@ -949,6 +934,8 @@ miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
   std::stable_sort(order.begin(), order.end(),
                    [&](int64_t a, int64_t b) { return cost(a) > cost(b); });
   int64_t roff = 0;
+  BatchTask* ptasks = batch_tasks(h->pin_tasks);
+  h->pin_tasks->count = (int)count;
   for (int64_t k = 0; k < count; ++k) {
     const int64_t i = order[(size_t)k];
     const qr_batch_item& it = items[i];
@@ -956,6 +943,9 @@ miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
     t.A = it.A;
     t.B = it.B;
     t.R = rbase + roff;
+    roff += (it.n * it.n + 31) & ~int64_t(31);
+    t.C = rbase + roff;
+    roff += (it.n * it.nrhs + 31) & ~int64_t(31);
     t.tau = nullptr;
     t.lda = it.lda;
     t.ldb = it.ldb;
@@ -964,15 +954,13 @@ miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
     t.nrhs = (int)it.nrhs;
     t.flags = kTaskWriteR;
     t.slot = (int)i;
-    roff += (it.n * (it.n + it.nrhs) + 31) & ~int64_t(31);
-    h->pin_tasks[k] = t;
+    ptasks[k] = t;
   }
-  hipError_t e = hipMemcpyAsync(dtasks, h->pin_tasks, count * sizeof(BatchTask),
+  hipError_t e = hipMemcpyAsync(dtable, h->pin_tasks, batch_table_bytes(count),
                                 hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipEventRecord(h->table_ev, s);
   if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched upload");
-  batched_ls(s, dtasks, (int)count, counter, dstatus, batched_grid(h->device, (int)count), bytes,
-             flops);
+  batched_ls(s, dtable, counter, dstatus, batched_grid(h->device, (int)count), bytes, flops);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched launch");
   if (!status) return MIQR_OK;

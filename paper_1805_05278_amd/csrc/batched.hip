@@ -38,7 +38,7 @@ __device__ void batch_factor(const BatchTask& t, double (*ybuf)[H], double* tbuf
   const bool keep = (t.flags & kTaskKeep) != 0;
   double* col = nullptr;
   if (own) col = c < n ? t.A + (int64_t)c * t.lda : t.B + (int64_t)(c - n) * t.ldb;
-  double* Rc = t.R + (int64_t)c * n;
+  double* Rc = c < n ? t.R + (int64_t)c * n : t.C + (int64_t)(c - n) * n;
   const int jmax = c < n ? c : n - 1;  // last row of R in column c
   if (own)
     for (int j = 0; j <= jmax; ++j) Rc[j] = 0.0;
@@ -158,13 +158,13 @@ __device__ void batch_apply(const BatchTask& t, double (*cbuf)[kBatchThreads]) {
         __builtin_amdgcn_wave_barrier();
       }
     }
-    double* Rk = t.R + (int64_t)(n + k) * n;
+    double* Rk = t.C + (int64_t)k * n;
     for (int j = l; j < n; j += 64) Rk[j] = cb[j];
     __builtin_amdgcn_wave_barrier();
   }
 }
 
-// R x = c for the nrhs right-hand sides in R's last columns; thread l owns row
+// R x = c for the nrhs right-hand sides held in C; thread l owns row
 // l.  Returns the 1-based index of the first zero diagonal entry (0 if none);
 // then B's top rows receive c unchanged.
 __device__ int batch_solve(const BatchTask& t, double (*xbuf)[kBatchMaxRhs], int* s_sing) {
@@ -179,7 +179,7 @@ __device__ int batch_solve(const BatchTask& t, double (*xbuf)[kBatchMaxRhs], int
   double cv[kBatchMaxRhs];
 #pragma unroll
   for (int k = 0; k < kBatchMaxRhs; ++k)
-    cv[k] = (k < nrhs && l < n) ? R[l + (int64_t)(n + k) * n] : 0.0;
+    cv[k] = (k < nrhs && l < n) ? t.C[l + (int64_t)k * n] : 0.0;
   if (sing == INT_MAX) {
     double rl = l < n ? R[l + (int64_t)(n - 1) * n] : 0.0;  // R[l, n-1]
     for (int i = n - 1; i >= 0; --i) {
@@ -201,12 +201,17 @@ __device__ int batch_solve(const BatchTask& t, double (*xbuf)[kBatchMaxRhs], int
     }
   }
   if (l < n)
-    for (int k = 0; k < nrhs; ++k) t.B[l + (int64_t)k * t.ldb] = cv[k];
+    for (int k = 0; k < nrhs; ++k) {
+      t.B[l + (int64_t)k * t.ldb] = cv[k];
+      if (t.X) t.X[l + (int64_t)k * n] = cv[k];
+    }
   return sing == INT_MAX ? 0 : sing + 1;
 }
 
-__global__ __launch_bounds__(kBatchThreads, 3) void k_batched_ls(const BatchTask* tasks, int count,
-                                                              int* counter, int* status) {
+__global__ __launch_bounds__(kBatchThreads, 3) void k_batched_ls(const BatchHeader* table,
+                                                                 int* counter, int* status) {
+  const int count = __builtin_amdgcn_readfirstlane(table->count);
+  const BatchTask* tasks = (const BatchTask*)(table + 1);
   __shared__ __align__(16) double ybuf[2][H];
   __shared__ double tbuf[2];
   __shared__ double xbuf[2][kBatchMaxRhs];
@@ -252,13 +257,12 @@ int batched_grid(int device, int count) {
   return (int)(count < g ? count : g);
 }
 
-void batched_ls(hipStream_t s, const BatchTask* tasks, int count, int* counter, int* status,
-                int grid, double bytes, double flops) {
-  if (count <= 0 || grid <= 0) return;
+void batched_ls(hipStream_t s, const BatchHeader* table, int* counter, int* status, int grid,
+                double bytes, double flops) {
+  if (grid <= 0) return;
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counter);
   TimedLaunch tl(s, "batched_ls", bytes, flops);
-  hipLaunchKernelGGL(k_batched_ls, dim3(grid), dim3(kBatchThreads), 0, s, tasks, count, counter,
-                     status);
+  hipLaunchKernelGGL(k_batched_ls, dim3(grid), dim3(kBatchThreads), 0, s, table, counter, status);
 }
 
 }  // namespace miqr
