@@ -86,6 +86,110 @@ def cpu_baseline(inputs):
                       "matrices of one step, without the LS solve (%.1f s)" % dt}
 
 
+def nominal_ls_flops(m, n, k):
+    """QR of A plus Q^T B and back substitution (nominal)."""
+    return 2.0 * m * n * n - 2.0 * n ** 3 / 3.0 + 4.0 * m * n * k + n * n * k
+
+
+def bench_batched(torch, miqr, synth, h, count=10000, seed=4242):
+    """The serving workload's problems (m in [64, 4096], n in [8, 256], 1-4
+    right-hand sides) solved in one batched call, inputs resident in HBM."""
+    trace = synth.serving_trace(count, 0.0, seed)
+    As = [synth.gaussian_device(r.m, r.n, 10 ** 6 + i) for i, r in enumerate(trace)]
+    Bs = [synth.gaussian_device(r.m, r.nrhs, 2 * 10 ** 6 + i) for i, r in enumerate(trace)]
+    warm = 512
+    h.lstsq_batched([a.clone() for a in As[:warm]], [b.clone() for b in Bs[:warm]])
+    torch.cuda.synchronize()
+    h.profile(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    st, _ = h.lstsq_batched(As, Bs, want_status=False)
+    e1.record()
+    torch.cuda.synchronize()
+    tot = h.profile_totals().get("batched_ls", {})
+    h.profile(False)
+    ms = e0.elapsed_time(e1)
+    flops = sum(nominal_ls_flops(r.m, r.n, r.nrhs) for r in trace)
+    kms = tot.get("ms", float("nan"))
+    return {"problems": count, "shapes": "m~U[64,4096], n~U[8,256] (m>=n), nrhs~U[1,4]",
+            "ms": ms, "solves_per_s": count / (ms * 1e-3), "gflops_nominal": flops / (ms * 1e-3) / 1e9,
+            "kernel_ms": kms, "kernel_tflops": flops / (kms * 1e-3) / 1e12 if kms == kms else None,
+            "kernel_frac_fp64_alu_peak": flops / (kms * 1e-3) / PEAK["fp64"] if kms == kms else None}
+
+
+def bench_serving(torch, miqr, synth, h, count=10000, qps=8000.0, seed=99):
+    """Open-loop Poisson stream through the serving loop: host (pinned) inputs,
+    arrival -> completion latency per request."""
+    import numpy as np
+    trace = synth.serving_trace(count, qps, seed)
+    P = 32
+    g = torch.Generator().manual_seed(seed)
+    poolA = [torch.randn((256, 4096), generator=g, dtype=torch.float64).pin_memory().t()
+             for _ in range(P)]
+    poolB = [torch.randn((4, 4096), generator=g, dtype=torch.float64).pin_memory().t()
+             for _ in range(P)]
+    X = [np.zeros((r.n, r.nrhs), order="F") for r in trace]
+    srv = miqr.Server(h, hbm_budget=16 << 30, max_batch=1024)
+    # Warm the path (graphs, pools) with a few requests first.
+    warm = 8
+    for i in range(warm):
+        r = trace[i]
+        srv.submit(poolA[i % P][:r.m, :r.n], poolB[i % P][:r.m, :r.nrhs], X[i])
+    got = 0
+    while got < warm:
+        got += len(srv.poll(wait=True))
+    recs = []
+    t0 = srv.clock()
+    idx = 0
+    while len(recs) < count:
+        now = srv.clock() - t0
+        if now > 300.0:
+            raise RuntimeError("serving run did not finish (%d of %d done)" % (len(recs), count))
+        while idx < count and trace[idx].arrival_s <= now:
+            r = trace[idx]
+            srv.submit(poolA[idx % P][:r.m, :r.n], poolB[idx % P][:r.m, :r.nrhs], X[idx])
+            idx += 1
+        recs.extend(srv.poll())
+    srv.close()
+    lat = np.array([d["end_s"] - d["submit_s"] for d in recs])
+    span = max(d["end_s"] for d in recs) - min(d["submit_s"] for d in recs)
+    flops = sum(nominal_ls_flops(r.m, r.n, r.nrhs) for r in trace)
+    h2d = sum(8.0 * r.m * (r.n + r.nrhs) for r in trace)
+    return {"requests": count, "qps_offered": qps, "solves_per_s": count / span,
+            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+            "mean_batch": float(np.mean([d["batch_size"] for d in recs])),
+            "gflops_nominal": flops / span / 1e9, "h2d_gb": h2d / 1e9,
+            "inputs": "pinned host memory (32 pooled 4096x256 N(0,1) matrices, leading m x n blocks)"}
+
+
+def bench_mixed(torch, miqr, synth, h, m=65536, n=2048, cond=1e2, seed=34001):
+    """Least squares on the conditioned 65536 x 2048 workload: FP64 against the
+    mixed forms, each to backward error <= 1e-13."""
+    A = synth.conditioned(m, n, cond, seed)
+    _, B = synth.ls_rhs(A, seed + 1, noise=1e-6, nrhs=1)
+    A0, B0 = miqr.to_colmajor(A), miqr.to_colmajor(B)
+    out = {"shape": [m, n], "cond": cond}
+    for name, prec in (("fp64", miqr.FP64), ("fp32", miqr.MIXED_FP32), ("bf16", miqr.MIXED_BF16)):
+        times = []
+        for rep in range(3):
+            Ad = miqr.colmajor(m, n)
+            Bd = miqr.colmajor(m, 1)
+            Ad.copy_(A0)
+            Bd.copy_(B0)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st, info = h.lstsq(Ad, Bd, h.opts(precision=prec))
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t)
+        best = min(times[1:])
+        out[name] = {"ms": best * 1e3, "solves_per_s": 1.0 / best, "status": st,
+                     "backward_error": info.backward_error, "iterations": info.iterations,
+                     "fallback": info.fallback}
+    out["speedup_fp32_vs_fp64"] = out["fp64"]["ms"] / out["fp32"]["ms"]
+    out["speedup_bf16_vs_fp64"] = out["fp64"]["ms"] / out["bf16"]["ms"]
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +199,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (PMC byte-counter scale)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the batched, serving and mixed-precision sections")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path "
@@ -202,6 +308,14 @@ def main():
         line["kernels"] = {k: {"ms_per_step": v["ms"] / args.steps,
                                "launches_per_step": v["launches"] / args.steps}
                            for k, v in sorted(totals.items(), key=lambda kv: -kv[1]["ms"])}
+    if not args.no_extras:
+        for key, fn in (("batched", bench_batched), ("serving", bench_serving),
+                        ("mixed_ls", bench_mixed)):
+            try:
+                line[key] = fn(torch, miqr, synth, h)
+            except Exception as exc:  # reported, never hidden
+                line[key] = {"error": "%s: %s" % (type(exc).__name__, exc)}
+            torch.cuda.empty_cache()
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(host)
     print(json.dumps(line))

@@ -168,7 +168,8 @@ miqr_status qr_form_q(miqr_handle handle, void *stream, int64_t m, int64_t n,
  * the solution is refined in FP64 against a device copy of the original A
  * (R-preconditioned conjugate gradients on the normal equations, FP64
  * residuals) until the backward error is <= 1e-13 and has stopped
- * decreasing (at most 50 iterations); if the 1e-13 gate is not met the problem
+ * decreasing (at most 100 iterations, fewer when the observed contraction
+ * cannot reach the gate in time); if the 1e-13 gate is not met the problem
  * is refactored in FP64 (info->fallback = 1, status MIQR_ENOCONV).
  *   info (host, may be NULL): when given, the call synchronises the stream and
  *   fills it.

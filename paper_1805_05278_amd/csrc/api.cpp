@@ -341,7 +341,8 @@ double backward_error_dev(hipStream_t s, int64_t m, int64_t n, int64_t k, const 
 // backward error beta(x) (worst right-hand side) is at most tol and has
 // stopped improving (below 4u, or less than halved by the last iteration), so
 // the result carries FP64 accuracy rather than just meeting the gate; it
-// fails over to the FP64 path if the gate is not met within maxit steps.
+// fails over to the FP64 path if the gate is not met within maxit steps, or
+// as soon as the observed contraction rate shows it will not be.
 struct MixedWs {
   double *T, *A0, *B0, *Rinv, *X, *Rr, *S, *P, *Tv, *Qv, *U, *W1, *W2, *sc, *nrm, *coef;
   int64_t scn;
@@ -386,7 +387,7 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
     w.scn = L.scratch;
   }
   const double tol = 1e-13, floor = 4.0 * 0x1p-53;
-  const int maxit = 50;
+  const int maxit = 100;
   copy_matrix(s, m, n, A, lda, w.A0, m);
   copy_matrix(s, m, k, B, ldb, w.B0, m);
   st = do_factor(h, s, m, n, A, lda, w.T, n, o, comp);
@@ -455,6 +456,7 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
     for (int64_t c = 0; c < k; ++c) gam[c] = hn[c];
     backward();
     double prev = worst;
+    std::vector<double> hist{worst};
     auto settled = [&]() { return worst <= tol && (worst <= floor || worst > 0.5 * prev); };
     bool done = worst <= floor;
     while (!done && iters < maxit && e == hipSuccess) {
@@ -485,6 +487,13 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
       prev = worst;
       backward();
       if (settled()) break;
+      // Give up early (and fall back) when the contraction over the last five
+      // iterations cannot reach the gate within the iteration cap.
+      hist.push_back(worst);
+      if (hist.size() >= 8) {
+        const double rate = std::pow(worst / hist[hist.size() - 6], 0.2);
+        if (!(rate < 1.0) || worst * std::pow(rate, maxit - iters) > tol) break;
+      }
       for (int64_t c = 0; c < k; ++c) {
         hc[k + c] = (gam[c] > 0.0) ? hn[c] / gam[c] : 0.0;
         gam[c] = hn[c];
