@@ -129,7 +129,8 @@ FactorLayout factor_layout(int64_t m, int64_t n, const Tuning& t) {
   const int64_t n2 = n - n1;
   L.wa = std::max<int64_t>(n1 * n2, 1);
   L.wb = L.wa;
-  L.scratch = std::max<int64_t>(int64_t(4) << 20, 4 * L.wa);
+  // Split-K partials: room for 512 splits of a 128 x 128 product.
+  L.scratch = std::max<int64_t>(int64_t(8) << 20, 4 * L.wa);
   L.total = L.tsqr + L.wa + L.wb + L.scratch + 4 * 32;
   return L;
 }
@@ -912,8 +913,8 @@ miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
       return fail(h, MIQR_EINVAL, "need 2^31 > m >= n >= 1" + at);
     if (it.nrhs < 1 || it.nrhs > kBatchMaxRhs)
       return fail(h, MIQR_EINVAL, "need 1 <= nrhs <= " + std::to_string(kBatchMaxRhs) + at);
-    if (it.n + it.nrhs > kBatchThreads)
-      return fail(h, MIQR_EINVAL, "need n + nrhs <= " + std::to_string(kBatchThreads) + at);
+    if (it.n + it.nrhs > kBatchMaxCols)
+      return fail(h, MIQR_EINVAL, "need n + nrhs <= " + std::to_string(kBatchMaxCols) + at);
     if (it.lda < it.m || it.ldb < it.m) return fail(h, MIQR_EINVAL, "leading dimension too small" + at);
     if (bad_ptr(it.A) || bad_ptr(it.B)) return fail(h, MIQR_EINVAL, "null pointer" + at);
     rtot += ((it.n * it.n + 31) & ~int64_t(31)) + ((it.n * it.nrhs + 31) & ~int64_t(31));

@@ -7,8 +7,9 @@
 
 namespace miqr {
 
-constexpr int kBatchRows = 64;     // row block height of the flat TSQR sweep
-constexpr int kBatchThreads = 320; // one thread per column: n + nrhs <= 320
+constexpr int kBatchRows = 64;      // row block height of the flat TSQR sweep
+constexpr int kBatchMaxCols = 320;  // n + nrhs limit
+constexpr int kBatchThreads = 2 * kBatchMaxCols;  // two threads per column
 constexpr int kBatchMaxRhs = 8;
 
 // Task flags.

@@ -11,14 +11,16 @@
 // factor of A and, in its last nrhs columns, the top n rows of Q^T B; back
 // substitution gives X.
 //
-// Thread c owns column c of [A | B]: the block's 64 entries in registers and
-// column c of R in global memory, which no other thread touches.  A step is
-// one reflector: the pivot thread builds y and tau and posts them in LDS; every
-// thread to its right forms its dot product with y locally (no cross-thread
-// reduction) and updates its column.  One barrier per step.
+// Two threads own column c of [A | B]: 32 rows each of the current block in
+// registers, and column c of R in global memory, which no other column
+// touches.  A step is one reflector: the pivot column posts its entries and
+// (tau, scale) in LDS; every column to its right forms its dot product with
+// them (32 products per thread plus one lane-pair sum, no workgroup
+// reduction) and updates itself.  One barrier per step.
 #include <climits>
 
 #include "batched.h"
+#include "common.h"
 #include "profiler.h"
 
 namespace miqr {
@@ -30,95 +32,134 @@ __global__ void k_batch_reset(int* counter) {
   if (threadIdx.x == 0) counter[0] = 0;
 }
 
-// Flat TSQR sweep of one problem (flags without kTaskApply).
-__device__ void batch_factor(const BatchTask& t, double (*ybuf)[H], double* tbuf) {
-  const int c = threadIdx.x;
+// Global-address-space views: loads and stores through them wait on the
+// vector memory counter only, so a prefetch stays in flight across LDS traffic.
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ gdouble* gp(double* p) { return (gdouble*)p; }
+
+// Adjacent-lane pair sum (quad_perm [1,0,3,2]) and even-lane broadcast
+// (quad_perm [0,0,2,2]) for the two threads that share a column.
+__device__ __forceinline__ double pair_sum(double v) { return v + dpp_mov<0xB1>(v); }
+__device__ __forceinline__ double from_even(double v) { return dpp_mov<0xA0>(v); }
+
+constexpr int HR = H / 2;  // rows of a block held by each of a column's two threads
+
+// Flat TSQR sweep of one problem (flags without kTaskApply).  Threads 2c and
+// 2c+1 hold rows [0, 32) and [32, 64) of column c of the current block; the
+// even thread also owns column c of R in global memory.  The pivot posts its
+// unscaled column and (tau, scale); the others fold the scale into their
+// update coefficient, so the pivot never rescales its column.
+__device__ void batch_factor(const BatchTask& t, double (*xs)[H], double (*coef)[2]) {
+  const int tid = threadIdx.x, c = tid >> 1, half = tid & 1;
+  const int wave = tid >> 6;
   const int n = t.n, N = n + t.nrhs, m = t.m;
   const bool own = c < N;
   const bool keep = (t.flags & kTaskKeep) != 0;
-  double* col = nullptr;
-  if (own) col = c < n ? t.A + (int64_t)c * t.lda : t.B + (int64_t)(c - n) * t.ldb;
-  double* Rc = c < n ? t.R + (int64_t)c * n : t.C + (int64_t)(c - n) * n;
+  gdouble* col = nullptr;
+  if (own) col = gp(c < n ? t.A + (int64_t)c * t.lda : t.B + (int64_t)(c - n) * t.ldb);
+  gdouble* Rc = gp(c < n ? t.R + (int64_t)c * n : t.C + (int64_t)(c - n) * n);
   const int jmax = c < n ? c : n - 1;  // last row of R in column c
-  if (own)
+  if (own && half == 0)
     for (int j = 0; j <= jmax; ++j) Rc[j] = 0.0;
   const int nblk = (m + H - 1) / H;
-  double x[H];
+  double x[HR];
+  double sc_own = 0.0;  // scale of this column's reflector in the current block
   for (int bk = 0; bk < nblk; ++bk) {
-    const int r0 = bk * H;
-    const int rows = min(H, m - r0);
+    const int r0 = bk * H + half * HR;
+    const int rows = max(0, min(HR, m - r0));
     if (own) {
-      if (rows == H) {
+      if (rows == HR) {
 #pragma unroll
-        for (int r = 0; r < H; ++r) x[r] = col[r0 + r];
+        for (int r = 0; r < HR; ++r) x[r] = col[r0 + r];
       } else {
 #pragma unroll
-        for (int r = 0; r < H; ++r) x[r] = r < rows ? col[r0 + r] : 0.0;
+        for (int r = 0; r < HR; ++r) x[r] = r < rows ? col[r0 + r] : 0.0;
       }
+    } else {
+#pragma unroll
+      for (int r = 0; r < HR; ++r) x[r] = 0.0;
     }
-    double rnext = own ? Rc[0] : 0.0;
+    // Partial sum of squares of the next pivot's column (column 0 first).
+    double s2 = 0.0;
+    if (c == 0) {
+#pragma unroll
+      for (int r = 0; r < HR; ++r) s2 += x[r] * x[r];
+    }
+    double rnext = (own && half == 0) ? Rc[0] : 0.0;
     for (int j = 0; j < n; ++j) {
       const int slot = j & 1;
-      const double rj = rnext;  // R[j, c]
-      if (own && j + 1 <= jmax) rnext = Rc[j + 1];
+      const double rj = from_even(rnext);  // R[j, c] in both threads of the column
+      if (own && half == 0 && j + 1 <= jmax) rnext = Rc[j + 1];
       if (c == j) {
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-        for (int r = 0; r < H; r += 4) {
-          s0 += x[r] * x[r];
-          s1 += x[r + 1] * x[r + 1];
-          s2 += x[r + 2] * x[r + 2];
-          s3 += x[r + 3] * x[r + 3];
-        }
-        const double sig2 = (s0 + s1) + (s2 + s3);
+        const double sig2 = pair_sum(s2);
         const double alpha = rj;
-        double tau = 0.0, beta = alpha;
+        double tau = 0.0, beta = alpha, sc = 0.0;
         if (sig2 != 0.0) {
           const double nrm = sqrt(alpha * alpha + sig2);
           beta = alpha >= 0.0 ? -nrm : nrm;
           tau = (beta - alpha) / beta;
-          const double sc = 1.0 / (alpha - beta);
-#pragma unroll
-          for (int r = 0; r < H; ++r) x[r] *= sc;
+          sc = 1.0 / (alpha - beta);
         }
-        Rc[j] = beta;
+        sc_own = sc;
 #pragma unroll
-        for (int r = 0; r < H; ++r) ybuf[slot][r] = x[r];
-        tbuf[slot] = tau;
-        if (keep) t.tau[(int64_t)bk * n + j] = tau;
+        for (int r = 0; r < HR; ++r) xs[slot][half * HR + r] = x[r];
+        if (half == 0) {
+          Rc[j] = beta;
+          coef[slot][0] = tau;
+          coef[slot][1] = sc;
+          if (keep) gp(t.tau)[(int64_t)bk * n + j] = tau;
+        }
       }
       __syncthreads();
       if (own && c > j) {
-        const double tau = tbuf[slot];
+        const double tau = coef[slot][0];
+        const bool next_wave = ((2 * (j + 1)) >> 6) == wave;  // holds the next pivot
         if (tau != 0.0) {
-          const double* y = ybuf[slot];
+          const double sc = coef[slot][1];
+          const double* y = xs[slot] + half * HR;
           double d0 = 0.0, d1 = 0.0, d2 = 0.0, d3 = 0.0;
 #pragma unroll
-          for (int r = 0; r < H; r += 4) {
+          for (int r = 0; r < HR; r += 4) {
             d0 += y[r] * x[r];
             d1 += y[r + 1] * x[r + 1];
             d2 += y[r + 2] * x[r + 2];
             d3 += y[r + 3] * x[r + 3];
           }
-          const double tw = tau * (rj + ((d0 + d1) + (d2 + d3)));
-          Rc[j] = rj - tw;
-          // Read y from LDS again rather than holding all 64 values live
-          // across both passes (keeps the kernel at three waves per SIMD).
+          const double w = rj + sc * pair_sum((d0 + d1) + (d2 + d3));
+          if (half == 0) Rc[j] = rj - tau * w;
+          const double f = tau * w * sc;
+          // Read y from LDS again for the update instead of holding it live
+          // across the pair sum (register pressure).
           asm volatile("" ::: "memory");
+          if (next_wave) {
+            double q0 = 0.0, q1 = 0.0;
 #pragma unroll
-          for (int r = 0; r < H; ++r) x[r] -= tw * y[r];
+            for (int r = 0; r < HR; r += 2) {
+              x[r] -= f * y[r];
+              x[r + 1] -= f * y[r + 1];
+              q0 += x[r] * x[r];
+              q1 += x[r + 1] * x[r + 1];
+            }
+            s2 = q0 + q1;
+          } else {
+#pragma unroll
+            for (int r = 0; r < HR; ++r) x[r] -= f * y[r];
+          }
+        } else if (next_wave) {
+          double q0 = 0.0, q1 = 0.0;
+#pragma unroll
+          for (int r = 0; r < HR; r += 2) {
+            q0 += x[r] * x[r];
+            q1 += x[r + 1] * x[r + 1];
+          }
+          s2 = q0 + q1;
         }
       }
     }
     if (keep && c < n) {
-      if (rows == H) {
 #pragma unroll
-        for (int r = 0; r < H; ++r) col[r0 + r] = x[r];
-      } else {
-#pragma unroll
-        for (int r = 0; r < H; ++r)
-          if (r < rows) col[r0 + r] = x[r];
-      }
+      for (int r = 0; r < HR; ++r)
+        if (r < rows) col[r0 + r] = sc_own * x[r];
     }
   }
 }
@@ -126,21 +167,21 @@ __device__ void batch_factor(const BatchTask& t, double (*ybuf)[H], double* tbuf
 // Replay stored reflectors on B only (kTaskApply).  Wave k (< nrhs) carries
 // right-hand side k with lane r holding row r of the block; a step is a
 // wave-wide dot product (DPP/shuffle sum), no workgroup barrier.
-__device__ void batch_apply(const BatchTask& t, double (*cbuf)[kBatchThreads]) {
+__device__ void batch_apply(const BatchTask& t, double (*cbuf)[kBatchMaxCols]) {
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int n = t.n, m = t.m;
   const int nblk = (m + H - 1) / H;
   double* cb = cbuf[w];  // running top n rows of Q^T b for this wave's column
   for (int k = w; k < t.nrhs; k += kBatchThreads / 64) {
-    double* b = t.B + (int64_t)k * t.ldb;
+    gdouble* b = gp(t.B + (int64_t)k * t.ldb);
     for (int j = l; j < n; j += 64) cb[j] = 0.0;
     __builtin_amdgcn_wave_barrier();
     for (int bk = 0; bk < nblk; ++bk) {
       const int r0 = bk * H;
       const bool in = r0 + l < m;
       double br = in ? b[r0 + l] : 0.0;
-      const double* Y = t.A + r0 + l;
-      const double* tb = t.tau + (int64_t)bk * n;
+      const gdouble* Y = gp(t.A + r0 + l);
+      const gdouble* tb = gp(t.tau + (int64_t)bk * n);
       double ynext = in ? Y[0] : 0.0;
       for (int j = 0; j < n; ++j) {
         const double y = ynext;
@@ -158,7 +199,7 @@ __device__ void batch_apply(const BatchTask& t, double (*cbuf)[kBatchThreads]) {
         __builtin_amdgcn_wave_barrier();
       }
     }
-    double* Rk = t.C + (int64_t)k * n;
+    gdouble* Rk = gp(t.C + (int64_t)k * n);
     for (int j = l; j < n; j += 64) Rk[j] = cb[j];
     __builtin_amdgcn_wave_barrier();
   }
@@ -170,7 +211,8 @@ __device__ void batch_apply(const BatchTask& t, double (*cbuf)[kBatchThreads]) {
 __device__ int batch_solve(const BatchTask& t, double (*xbuf)[kBatchMaxRhs], int* s_sing) {
   const int l = threadIdx.x;
   const int n = t.n, nrhs = t.nrhs;
-  const double* R = t.R;
+  const gdouble* R = gp(t.R);
+  const gdouble* C = gp(t.C);
   if (l == 0) *s_sing = INT_MAX;
   __syncthreads();
   if (l < n && R[l + (int64_t)l * n] == 0.0) atomicMin(s_sing, l);
@@ -179,7 +221,7 @@ __device__ int batch_solve(const BatchTask& t, double (*xbuf)[kBatchMaxRhs], int
   double cv[kBatchMaxRhs];
 #pragma unroll
   for (int k = 0; k < kBatchMaxRhs; ++k)
-    cv[k] = (k < nrhs && l < n) ? t.C[l + (int64_t)k * n] : 0.0;
+    cv[k] = (k < nrhs && l < n) ? C[l + (int64_t)k * n] : 0.0;
   if (sing == INT_MAX) {
     double rl = l < n ? R[l + (int64_t)(n - 1) * n] : 0.0;  // R[l, n-1]
     for (int i = n - 1; i >= 0; --i) {
@@ -202,20 +244,20 @@ __device__ int batch_solve(const BatchTask& t, double (*xbuf)[kBatchMaxRhs], int
   }
   if (l < n)
     for (int k = 0; k < nrhs; ++k) {
-      t.B[l + (int64_t)k * t.ldb] = cv[k];
-      if (t.X) t.X[l + (int64_t)k * n] = cv[k];
+      gp(t.B)[l + (int64_t)k * t.ldb] = cv[k];
+      if (t.X) gp(t.X)[l + (int64_t)k * n] = cv[k];
     }
   return sing == INT_MAX ? 0 : sing + 1;
 }
 
-__global__ __launch_bounds__(kBatchThreads, 3) void k_batched_ls(const BatchHeader* table,
+__global__ __launch_bounds__(kBatchThreads) void k_batched_ls(const BatchHeader* table,
                                                                  int* counter, int* status) {
   const int count = __builtin_amdgcn_readfirstlane(table->count);
   const BatchTask* tasks = (const BatchTask*)(table + 1);
   __shared__ __align__(16) double ybuf[2][H];
-  __shared__ double tbuf[2];
+  __shared__ double tbuf[2][2];
   __shared__ double xbuf[2][kBatchMaxRhs];
-  __shared__ double cbuf[kBatchThreads / 64][kBatchThreads];
+  __shared__ double cbuf[kBatchThreads / 64][kBatchMaxCols];
   __shared__ int s_idx, s_sing;
   for (;;) {
     if (threadIdx.x == 0) s_idx = atomicAdd(counter, 1);
@@ -235,7 +277,7 @@ __global__ __launch_bounds__(kBatchThreads, 3) void k_batched_ls(const BatchHead
     if ((t.flags & kTaskWriteR) && st == 0) {
       const int c = threadIdx.x;
       if (c < t.n)
-        for (int j = 0; j <= c; ++j) t.A[j + (int64_t)c * t.lda] = t.R[j + (int64_t)c * t.n];
+        for (int j = 0; j <= c; ++j) gp(t.A)[j + (int64_t)c * t.lda] = gp(t.R)[j + (int64_t)c * t.n];
     }
     if (threadIdx.x == 0) status[t.slot] = st;
     __syncthreads();

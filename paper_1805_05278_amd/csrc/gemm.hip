@@ -337,13 +337,30 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   }
 }
 
-__global__ void k_splitk_reduce(const double* P, int nsplit, int64_t M, int64_t N, double beta,
-                                double* C, int64_t ldc) {
+// C = sum_z P[z] (+ beta C).  A block covers 64 consecutive elements with 4
+// groups of splits: group g sums partials g, g + 4, g + 8, ... in order, and
+// the four group sums are added in a fixed order, so the result does not
+// depend on scheduling.
+__global__ __launch_bounds__(256) void k_splitk_reduce(const double* P, int nsplit, int64_t M,
+                                                       int64_t N, double beta, double* C,
+                                                       int64_t ldc) {
+  __shared__ double part[4][64];
   const int64_t MN = M * N;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < MN;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int z = 0; z < nsplit; ++z) s += P[z * MN + e];
+  const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t e = (int64_t)blockIdx.x * 64 + lane;
+  double s0 = 0.0, s1 = 0.0;
+  if (e < MN) {
+    int z = g;
+    for (; z + 4 < nsplit; z += 8) {
+      s0 += P[(int64_t)z * MN + e];
+      s1 += P[(int64_t)(z + 4) * MN + e];
+    }
+    if (z < nsplit) s0 += P[(int64_t)z * MN + e];
+  }
+  part[g][lane] = s0 + s1;
+  __syncthreads();
+  if (g == 0 && e < MN) {
+    const double s = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
     const int64_t i = e % M, j = e / M;
     double* cp = C + i + j * ldc;
     *cp = (beta == 0.0) ? s : s + beta * *cp;
@@ -419,7 +436,7 @@ hipError_t gemm(const GemmDesc& d, hipStream_t s, double* scratch, int64_t scrat
   if (nsplit > 1) {
     const int64_t MN = d.M * d.N;
     TimedLaunch tr(s, "gemm_splitk_reduce", 8.0 * (double)MN * (nsplit + 2), (double)MN * nsplit);
-    const int blocks = (int)std::min<int64_t>((MN + 255) / 256, 4096);
+    const int blocks = (int)((MN + 63) / 64);
     hipLaunchKernelGGL(k_splitk_reduce, dim3(blocks), dim3(256), 0, s, (const double*)scratch,
                        (int)nsplit, d.M, d.N, d.beta, d.C, d.ldc);
   }

@@ -429,7 +429,7 @@ miqr_status qr_server_create(miqr_handle h, const qr_server_opts* o, miqr_server
     h->err = "max_batch above 2^20";
     return MIQR_EINVAL;
   }
-  if (stage < (int64_t)kBatchThreads * kBatchThreads * 2) {
+  if (stage < (int64_t)kBatchMaxCols * kBatchMaxCols * 2) {
     h->err = "stage_bytes too small for one request";
     return MIQR_EINVAL;
   }
@@ -481,7 +481,7 @@ miqr_status qr_server_submit(miqr_server_handle s, int64_t m, int64_t n, int64_t
   if (!s || !id) return MIQR_EINVAL;
   s->h->err.clear();
   if (n < 1 || m < n || m > INT32_MAX) return sfail(s, MIQR_EINVAL, "need 2^31 > m >= n >= 1");
-  if (nrhs < 1 || nrhs > kBatchMaxRhs || n + nrhs > kBatchThreads)
+  if (nrhs < 1 || nrhs > kBatchMaxRhs || n + nrhs > kBatchMaxCols)
     return sfail(s, MIQR_EINVAL, "need 1 <= nrhs <= 8 and n + nrhs <= 320");
   if (check_host(A, lda, m) || check_host(B, ldb, m) || check_host(X, ldx, n))
     return sfail(s, MIQR_EINVAL, "null pointer or leading dimension too small");
@@ -520,7 +520,7 @@ miqr_status qr_server_resolve(miqr_server_handle s, int64_t factored, int64_t nr
   const Req& p = it->second;
   if (p.state != DONE) return sfail(s, MIQR_EBUSY, "factorisation not finished yet");
   if (p.status != 0) return sfail(s, MIQR_ESINGULAR, "kept factorisation is singular");
-  if (nrhs < 1 || nrhs > kBatchMaxRhs || p.n + nrhs > kBatchThreads)
+  if (nrhs < 1 || nrhs > kBatchMaxRhs || p.n + nrhs > kBatchMaxCols)
     return sfail(s, MIQR_EINVAL, "need 1 <= nrhs <= 8 and n + nrhs <= 320");
   if (check_host(B, ldb, p.m) || check_host(X, ldx, p.n))
     return sfail(s, MIQR_EINVAL, "null pointer or leading dimension too small");

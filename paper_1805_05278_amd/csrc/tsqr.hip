@@ -48,12 +48,13 @@ struct ChainQRArgs {
   double* R;       // per chain / node
 };
 
-// Sum over N consecutive lanes (N = 16 or 32), result in every lane: quad
+// Sum over N consecutive lanes (N = 8, 16 or 32), result in every lane: quad
 // sums and half-row / row mirrors through DPP, then (N = 32) an exchange
 // between the two 16-lane rows of a 32-lane group through ds_swizzle.
 template <int N>
 __device__ __forceinline__ double group_sum(double v) {
   v = oct_sum(v);
+  if (N == 8) return v;
   v += dpp_mov<0x140>(v);  // row_mirror: lane i <-> 15 - i
   if (N == 32) {
     const unsigned long long b = (unsigned long long)__double_as_longlong(v);
@@ -65,7 +66,7 @@ __device__ __forceinline__ double group_sum(double v) {
   return v;
 }
 
-// Register layout of a block of H rows (H = 128 or 256) in a 512-thread
+// Register layout of a block of H rows (H = 64, 128 or 256) in a 512-thread
 // workgroup: RG = H / 8 row groups of 8 consecutive rows; thread t holds rows
 // 8 rg .. 8 rg + 7 (rg = t % RG) of CPT = RG / 8 columns cg CPT .. cg CPT +
 // CPT - 1 (cg = t / RG).  The RG threads of a column group sit in one wave,
@@ -795,7 +796,15 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     ChainQRArgs a{p.levels[lev - 1].R, kNB, 0, lv.nblocks, lv.chain_len, nbr, lv.Y, lv.T, lv.R};
     TimedLaunch tl(s, "tsqr_chain_qr_tree", tri * (2.0 * lv.nblocks + 3.0 * lv.nchains),
                    3.0 * (double)lv.nblocks * nbr * nbr * nbr);
-    hipLaunchKernelGGL((k_chain_qr<kYL, false>), dim3(lv.nchains), dim3(512), 0, s, a);
+    // A node stacks (arity - 1) child R factors; the kernel's register
+    // layout is sized to that height.
+    const int stacked = (lv.chain_len - 1) * nbr;
+    if (stacked <= 64)
+      hipLaunchKernelGGL((k_chain_qr<64, false>), dim3(lv.nchains), dim3(512), 0, s, a);
+    else if (stacked <= 128)
+      hipLaunchKernelGGL((k_chain_qr<128, false>), dim3(lv.nchains), dim3(512), 0, s, a);
+    else
+      hipLaunchKernelGGL((k_chain_qr<kYL, false>), dim3(lv.nchains), dim3(512), 0, s, a);
   }
   // Householder reconstruction at the root.
   const int nq = Q ? 2 * nbr : nbr;
@@ -835,10 +844,18 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     d.nq = nq;
     TimedLaunch tl(s, "tsqr_down_tree", 8.0 * nbr * nq * 2.0 * lv.nblocks + tri * 2.0 * lv.nblocks,
                    3.0 * (double)lv.nblocks * nbr * nbr * nq);
-    if (nq > kNB)
-      hipLaunchKernelGGL((k_chain_down<4, 128, false>), dim3(lv.nchains), dim3(256), 0, s, d);
-    else
-      hipLaunchKernelGGL((k_chain_down<4, 64, false>), dim3(lv.nchains), dim3(256), 0, s, d);
+    const int stacked = (lv.chain_len - 1) * nbr;  // rows of -Y M per node
+    if (stacked <= 64) {
+      if (nq > kNB)
+        hipLaunchKernelGGL((k_chain_down<1, 128, false>), dim3(lv.nchains), dim3(256), 0, s, d);
+      else
+        hipLaunchKernelGGL((k_chain_down<1, 64, false>), dim3(lv.nchains), dim3(256), 0, s, d);
+    } else {
+      if (nq > kNB)
+        hipLaunchKernelGGL((k_chain_down<4, 128, false>), dim3(lv.nchains), dim3(256), 0, s, d);
+      else
+        hipLaunchKernelGGL((k_chain_down<4, 64, false>), dim3(lv.nchains), dim3(256), 0, s, d);
+    }
   }
   {
     const TsqrLevel& l0 = p.levels[0];
