@@ -28,7 +28,8 @@ PEAK = {"hbm": 8.0e12, "fp64": 78.6e12, "fp32": 157.3e12}
 # kernel -> arithmetic unit its flops run on
 KERNEL_UNIT = {"gemm_f64": ("mfma", "fp64"), "gemm_f32": ("mfma", "fp32"),
                "tsqr_down_leaf": ("mfma", "fp64"), "tsqr_down_tree": ("mfma", "fp64"),
-               "tsqr_chain_qr_leaf": ("alu", "fp64"), "tsqr_chain_qr_tree": ("alu", "fp64"),
+               "tsqr_chain_qr_leaf": ("alu", "fp64"), "tsqr_chain_qr_leaf_rest": ("alu", "fp64"),
+               "tsqr_chain_qr_tree": ("alu", "fp64"), "batched_ls": ("alu", "fp64"),
                "tsqr_hr_root": ("alu", "fp64"), "trsm_diag": ("alu", "fp64"),
                "gemm_splitk_reduce": ("alu", "fp64")}
 

@@ -220,8 +220,12 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
 }
 
 // LEAF: the chain walks row blocks of the panel (else stacked child R's).
-template <int H, bool LEAF>
-__global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
+// PART (leaf only): 0 the whole chain; 1 only its first block (local QR);
+// 2 the blocks after the first, starting from the R that part 1 left in the
+// chain's R slot.  Parts 1 and 2 are separate launches so that part 2, which
+// holds no first-block state, fits two workgroups per CU.
+template <int H, bool LEAF, int PART>
+__device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
   constexpr int RG = Lay<H>::RG, CPT = Lay<H>::CPT;
   const int t = threadIdx.x, rg = t % RG, cg = t / RG;
   const int chain = blockIdx.x;
@@ -238,6 +242,7 @@ __global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
     const int r = i % kNB, cc = i / kNB;
     double v = 0.0;
     if (!LEAF && r < nbr && cc < nbr) v = a.X[(int64_t)b0 * kTS + i];
+    if (LEAF && PART == 2 && r <= cc && cc < nbr) v = a.R[(int64_t)chain * kTS + i];
     Rs[r][cc] = v;
     Gs[r][cc] = 0.0;
   }
@@ -245,7 +250,9 @@ __global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
 
   double x[CPT][8];
   if constexpr (LEAF) {
-    for (int b = b0; b < b1; ++b) {
+    const int bs = PART == 2 ? b0 + 1 : b0;
+    const int be = PART == 1 ? b0 + 1 : b1;
+    for (int b = bs; b < be; ++b) {
       const bool first = b == b0;
       const int64_t rstart = ((int64_t)b * a.xrows) / a.nblocks;
       const int rows = (int)((((int64_t)b + 1) * a.xrows) / a.nblocks - rstart);
@@ -258,8 +265,12 @@ __global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
         for (int s = 0; s < 8; ++s)
           x[u][s] = (c < nbr && 8 * rg + s < rows) ? src[s + (int64_t)c * ld] : 0.0;
       }
-      if (first) qr_step<H, true>(x, nbr, Rs, Gs, vbuf, taus, Wt);
-      else qr_step<H, false>(x, nbr, Rs, Gs, vbuf, taus, Wt);
+      if constexpr (PART != 2) {
+        if (first) qr_step<H, true>(x, nbr, Rs, Gs, vbuf, taus, Wt);
+      }
+      if constexpr (PART != 1) {
+        if (!first) qr_step<H, false>(x, nbr, Rs, Gs, vbuf, taus, Wt);
+      }
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
         const int c = cg * CPT + u;
@@ -273,7 +284,7 @@ __global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
           const int r = i % kNB, cc = i / kNB;
           Tb[i] = (r <= cc && cc < nbr) ? Gs[r][cc] : 0.0;
         }
-      } else {
+      } else if (PART != 2) {
         // Z = T V_top^T (upper triangular) in place of T; Rs holds V_top
         // (unit lower top nbr x nbr part of the block's basis) meanwhile.
         if (rg < kNB / 8) {
@@ -354,6 +365,17 @@ __global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
     const int r = i % kNB, cc = i / kNB;
     a.R[(int64_t)chain * kTS + i] = (r <= cc && cc < nbr) ? Rs[r][cc] : 0.0;
   }
+}
+
+template <int H, bool LEAF, int PART>
+__global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
+  chain_qr_body<H, LEAF, PART>(a);
+}
+
+// Blocks after the first of each leaf chain, at two workgroups per CU.
+template <int H>
+__global__ __launch_bounds__(512, 4) void k_chain_qr_rest(ChainQRArgs a) {
+  chain_qr_body<H, true, 2>(a);
 }
 
 struct HRArgs {
@@ -730,10 +752,13 @@ TsqrPlan tsqr_plan(int64_t rows, int nbr, int leaf_rows, int chain, int arity, d
   TsqrPlan p;
   p.rows = rows;
   p.nbr = nbr;
-  if (leaf_rows != 128 && leaf_rows != 256) leaf_rows = (rows >= 256 * 1024) ? 256 : 128;
+  if (leaf_rows != 128 && leaf_rows != 256) leaf_rows = (rows >= 256 * 64) ? 256 : 128;
   p.leaf_rows = leaf_rows;
   const int64_t P0 = std::max<int64_t>(1, (rows + leaf_rows - 1) / leaf_rows);
-  if (chain <= 0) chain = (int)std::max<int64_t>(1, std::min<int64_t>(8, P0 / 1024));
+  // Chains of up to four blocks once there are enough blocks to keep every
+  // CU busy (measured best for 2^18..2^20 rows; longer chains starve the
+  // second leaf launch of workgroups).
+  if (chain <= 0) chain = (int)std::max<int64_t>(1, std::min<int64_t>(4, P0 / 256));
   // A node stacks arity - 1 child R factors (nbr rows each) in kYL rows.
   const int max_arity = 1 + kYL / std::max(nbr, 1);
   if (arity < 2) arity = std::min(max_arity, 5);
@@ -783,13 +808,27 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     const TsqrLevel& l0 = p.levels[0];
     ChainQRArgs a{P, ldp, p.rows, l0.nblocks, l0.chain_len, nbr, nullptr, l0.T, l0.R};
     // Read A, write V; write T per block and R per chain.  Flops: QR 2 m nb^2
-    // plus the Gram products for T, m nb^2.
-    TimedLaunch tl(s, "tsqr_chain_qr_leaf", 2.0 * pan + tri * (l0.nblocks + l0.nchains),
-                   3.0 * (double)p.rows * nbr * nbr);
-    if (p.leaf_rows == 256)
-      hipLaunchKernelGGL((k_chain_qr<256, true>), dim3(l0.nchains), dim3(512), 0, s, a);
-    else
-      hipLaunchKernelGGL((k_chain_qr<128, true>), dim3(l0.nchains), dim3(512), 0, s, a);
+    // plus the Gram products for T, m nb^2.  First blocks and the rest of
+    // each chain are separate launches; the byte and flop counts are split
+    // by the share of rows.
+    const double f1 = (double)l0.nchains / l0.nblocks;
+    {
+      TimedLaunch tl(s, "tsqr_chain_qr_leaf", 2.0 * pan * f1 + tri * 2.0 * l0.nchains,
+                     3.0 * (double)p.rows * nbr * nbr * f1);
+      if (p.leaf_rows == 256)
+        hipLaunchKernelGGL((k_chain_qr<256, true, 1>), dim3(l0.nchains), dim3(512), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_chain_qr<128, true, 1>), dim3(l0.nchains), dim3(512), 0, s, a);
+    }
+    if (l0.chain_len > 1) {
+      TimedLaunch tl(s, "tsqr_chain_qr_leaf_rest",
+                     2.0 * pan * (1.0 - f1) + tri * (l0.nblocks - l0.nchains + 2.0 * l0.nchains),
+                     3.0 * (double)p.rows * nbr * nbr * (1.0 - f1));
+      if (p.leaf_rows == 256)
+        hipLaunchKernelGGL((k_chain_qr_rest<256>), dim3(l0.nchains), dim3(512), 0, s, a);
+      else
+        hipLaunchKernelGGL((k_chain_qr_rest<128>), dim3(l0.nchains), dim3(512), 0, s, a);
+    }
   }
   for (int lev = 1; lev <= L; ++lev) {
     const TsqrLevel& lv = p.levels[lev];
@@ -800,11 +839,11 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     // layout is sized to that height.
     const int stacked = (lv.chain_len - 1) * nbr;
     if (stacked <= 64)
-      hipLaunchKernelGGL((k_chain_qr<64, false>), dim3(lv.nchains), dim3(512), 0, s, a);
+      hipLaunchKernelGGL((k_chain_qr<64, false, 0>), dim3(lv.nchains), dim3(512), 0, s, a);
     else if (stacked <= 128)
-      hipLaunchKernelGGL((k_chain_qr<128, false>), dim3(lv.nchains), dim3(512), 0, s, a);
+      hipLaunchKernelGGL((k_chain_qr<128, false, 0>), dim3(lv.nchains), dim3(512), 0, s, a);
     else
-      hipLaunchKernelGGL((k_chain_qr<kYL, false>), dim3(lv.nchains), dim3(512), 0, s, a);
+      hipLaunchKernelGGL((k_chain_qr<kYL, false, 0>), dim3(lv.nchains), dim3(512), 0, s, a);
   }
   // Householder reconstruction at the root.
   const int nq = Q ? 2 * nbr : nbr;

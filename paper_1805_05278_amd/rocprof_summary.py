@@ -31,8 +31,10 @@ COPY_BYTES = 8.0 * (1 << 27)
 
 # Demangled kernel symbol -> the name the library's event timer uses.
 _PATTERNS = [
-    (r"k_chain_qr<\d+, true>", "tsqr_chain_qr_leaf"),
-    (r"k_chain_qr<\d+, false>", "tsqr_chain_qr_tree"),
+    (r"k_chain_qr<\d+, true, \d+>", "tsqr_chain_qr_leaf"),
+    (r"k_chain_qr_rest<\d+>", "tsqr_chain_qr_leaf_rest"),
+    (r"k_chain_qr<\d+, false, \d+>", "tsqr_chain_qr_tree"),
+    (r"k_batched_ls", "batched_ls"),
     (r"k_tsqr_hr\b", "tsqr_hr_root"),
     (r"k_chain_down<\d+, \d+, false>", "tsqr_down_tree"),
     (r"k_chain_down<\d+, \d+, true>", "tsqr_down_leaf"),
