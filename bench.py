@@ -6,7 +6,9 @@ least-squares solve on the factors.
 One step = factor a 1,048,576 x 64 and a 262,144 x 256 Gaussian matrix in place
 (each with its explicit thin Q), then solve one least-squares right-hand side
 with the 262,144 x 256 factors (apply Q^T, back substitution).  Every step works
-on its own copy of the inputs, prepared in HBM before the timed region.
+on its own copy of the inputs, prepared in HBM before the timed region.  The two
+factorisations are independent and run on two streams with a handle each
+(--serial: one stream, one after the other).
 
 value = nominal QR flops (2 m n^2 - 2 n^3 / 3, summed over both matrices) per
 second.  The JSON line also carries the roofline of the dominant kernel
@@ -200,6 +202,8 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no per-kernel event timing")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (PMC byte-counter scale)")
+    ap.add_argument("--serial", action="store_true",
+                    help="run the step's two factorisations one after the other on one stream")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the batched, serving and mixed-precision sections")
     args = ap.parse_args()
@@ -215,7 +219,14 @@ def main():
     import synth
 
     dev = torch.device("cuda:0")
-    h = miqr.Handle(0)
+    # The two factorisations of a step are independent: each gets its own
+    # handle (workspace) and stream, so one's latency-bound phases (tree
+    # levels, reconstruction root) overlap the other's wide kernels.
+    h1, h = miqr.Handle(0), miqr.Handle(0)
+    if args.serial:
+        streams = [torch.cuda.current_stream()] * 2
+    else:
+        streams = [torch.cuda.Stream(), torch.cuda.Stream()]
     host = [synth.gaussian(m, n, 2000 + i) for i, (m, n) in enumerate(SHAPES)]
     pristine = [miqr.to_colmajor(A) for A in host]
     m2, n2 = SHAPES[1]
@@ -238,38 +249,70 @@ def main():
     opts = [h.opts(Q=Q) for Q in Qs]
 
     def step(As, b):
-        for A, T, o in zip(As, Ts, opts):
-            h.factor(A, T, o)
-        h.apply_q("T", As[1], Ts[1], b)
-        h.solve_r(As[1], b[:n2])
+        with torch.cuda.stream(streams[0]):
+            h1.factor(As[0], Ts[0], opts[0])
+        with torch.cuda.stream(streams[1]):
+            h.factor(As[1], Ts[1], opts[1])
+            h.apply_q("T", As[1], Ts[1], b)
+            h.solve_r(As[1], b[:n2])
 
     work = fresh()
     for _ in range(args.warmup):
         for A, P in zip(work[0], pristine):
             A.copy_(P)
         work[1].copy_(b_pristine)
+        torch.cuda.synchronize()
         step(*work)
-    torch.cuda.synchronize()
-    batches = [fresh() for _ in range(args.steps)]
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+    def measure(streams):
+        """Time args.steps steps on `streams`; returns (ms per step, wall s,
+        per-kernel totals, last step's outputs)."""
+        def step(As, b):
+            with torch.cuda.stream(streams[0]):
+                h1.factor(As[0], Ts[0], opts[0])
+            with torch.cuda.stream(streams[1]):
+                h.factor(As[1], Ts[1], opts[1])
+                h.apply_q("T", As[1], Ts[1], b)
+                h.solve_r(As[1], b[:n2])
 
-    if not args.no_profile:
-        h.profile(True)
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    e0.record()
-    for As, b in batches:
-        step(As, b)
-    e1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    ms = e0.elapsed_time(e1) / args.steps
-    totals = h.profile_totals() if not args.no_profile else {}
-    h.profile(False)
+        batches = [fresh() for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        if not args.no_profile:
+            h1.profile(True)
+            h.profile(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        main = torch.cuda.current_stream()
+        t0 = time.perf_counter()
+        e0.record(main)
+        for st in streams:
+            st.wait_stream(main)
+        for As, b in batches:
+            step(As, b)
+        for st in streams:
+            main.wait_stream(st)
+        e1.record(main)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        totals = {}
+        if not args.no_profile:
+            for hh in (h1, h):
+                for k, v in hh.profile_totals().items():
+                    t = totals.setdefault(k, dict(ms=0.0, launches=0, bytes=0.0, flops=0.0))
+                    for f in t:
+                        t[f] += v[f]
+        h1.profile(False)
+        h.profile(False)
+        return e0.elapsed_time(e1) / args.steps, wall, totals, batches[-1]
+
+    ms, wall, totals, last = measure(streams)
+    serial = None
+    if not args.serial:
+        one = torch.cuda.current_stream()
+        serial = measure([one, one])
 
     # Spot check of the last step against simple invariants (not timed).
-    As, b = batches[-1]
+    As, b = last
     R1 = torch.triu(As[0][:64, :64])
     Qr = Qs[0]
     rec = float(torch.linalg.norm(Qr[:4096] @ R1 - pristine[0][:4096]) /
@@ -301,9 +344,16 @@ def main():
         "data": "synthetic: i.i.d. N(0,1) from numpy PCG64 seeds 2000/2001",
         "config": {"workload": "tall-skinny QR + thin Q: 1048576x64 and 262144x256, "
                                "plus one least-squares RHS on the 262144x256 factors",
+                   "streams": 1 if args.serial else 2,
                    "fraction_of_fp64_peak": value * 1e9 / PEAK["fp64"],
                    "wall_s": wall, "recon_err_top4096": rec},
     }
+    if serial is not None:
+        sms, swall, stot, _ = serial
+        line["serial"] = {"ms_per_step": sms, "value": flops / (sms * 1e-3) / 1e9,
+                          "note": "same step on one stream, the two factorisations in turn"}
+        if stot:
+            line["serial"]["roofline"] = roofline(stot, args.steps)
     if totals:
         line["roofline"] = roofline(totals, args.steps)
         line["kernels"] = {k: {"ms_per_step": v["ms"] / args.steps,
@@ -321,6 +371,7 @@ def main():
         line["cpu_baseline"] = cpu_baseline(host)
     print(json.dumps(line))
     h.close()
+    h1.close()
 
 
 if __name__ == "__main__":

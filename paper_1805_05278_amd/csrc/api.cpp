@@ -760,10 +760,11 @@ miqr_status qr_form_q(miqr_handle h, void* stream, int64_t m, int64_t n, const d
   d.A = T; d.lda = ldt; d.maskA = MASK_UPPER; d.B = VR; d.ldb = lda; d.maskB = MASK_UNIT_LOWER;
   d.C = W; d.ldc = n;
   hipError_t e = gemm(d, s, sc, scratch_n);
-  set_identity(s, m, n, Q, ldq);
   if (e == hipSuccess) {
+    // Q = [I; 0] - V W in one pass (the identity is added in the epilogue).
     d = GemmDesc();
-    d.ta = 'N'; d.tb = 'N'; d.M = m; d.N = n; d.K = n; d.alpha = -1.0; d.beta = 1.0;
+    d.ta = 'N'; d.tb = 'N'; d.M = m; d.N = n; d.K = n; d.alpha = -1.0; d.beta = 0.0;
+    d.add_identity = 1;
     d.A = VR; d.lda = lda; d.maskA = MASK_UNIT_LOWER; d.B = W; d.ldb = n; d.C = Q; d.ldc = ldq;
     e = gemm(d, s, sc, scratch_n);
   }

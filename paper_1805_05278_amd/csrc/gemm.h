@@ -28,6 +28,7 @@ struct GemmDesc {
   double* C = nullptr;
   int64_t ldc = 0;
   int compute = COMPUTE_F64;
+  int add_identity = 0;  // C(i, i) += 1 after the product (with beta == 0: C = alpha AB + I)
 };
 
 // C = alpha op(A) op(B) + beta C (beta == 0: C is not read).  `scratch` holds

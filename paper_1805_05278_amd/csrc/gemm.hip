@@ -36,6 +36,7 @@ struct GemmArgs {
   int64_t ldc;
   double* P;  // split-K partials (M x N each) or null
   int maskA, maskB;
+  int add_identity;
 };
 
 template <int CMP>
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         if (!row_ok || j >= g.N) continue;
         const double v = g.alpha * (double)acc[a][b][r];
         if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = v;
-        else g.C[i + j * g.ldc] = v + g.beta * cv[b][r];
+        else g.C[i + j * g.ldc] = v + g.beta * cv[b][r] + ((g.add_identity && i == j) ? 1.0 : 0.0);
       }
   }
 }
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         if (!row_ok || j >= g.N) continue;
         const double v = g.alpha * (double)acc[a][b][r];
         if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = v;
-        else g.C[i + j * g.ldc] = v + g.beta * cv[b][r];
+        else g.C[i + j * g.ldc] = v + g.beta * cv[b][r] + ((g.add_identity && i == j) ? 1.0 : 0.0);
       }
   }
 }
@@ -343,7 +344,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 // depend on scheduling.
 __global__ __launch_bounds__(256) void k_splitk_reduce(const double* P, int nsplit, int64_t M,
                                                        int64_t N, double beta, double* C,
-                                                       int64_t ldc) {
+                                                       int64_t ldc, int add_identity) {
   __shared__ double part[4][64];
   const int64_t MN = M * N;
   const int lane = threadIdx.x & 63, g = threadIdx.x >> 6;
@@ -363,7 +364,7 @@ __global__ __launch_bounds__(256) void k_splitk_reduce(const double* P, int nspl
     const double s = ((part[0][lane] + part[1][lane]) + part[2][lane]) + part[3][lane];
     const int64_t i = e % M, j = e / M;
     double* cp = C + i + j * ldc;
-    *cp = (beta == 0.0) ? s : s + beta * *cp;
+    *cp = ((beta == 0.0) ? s : s + beta * *cp) + ((add_identity && i == j) ? 1.0 : 0.0);
   }
 }
 
@@ -413,7 +414,7 @@ hipError_t gemm(const GemmDesc& d, hipStream_t s, double* scratch, int64_t scrat
   kchunk = (kchunk + 31) / 32 * 32;
   nsplit = (d.K + kchunk - 1) / kchunk;
   GemmArgs g{d.M, d.N, d.K, kchunk, d.alpha, d.beta, d.A, d.lda, d.B, d.ldb,
-             d.C, d.ldc, nsplit > 1 ? scratch : nullptr, d.maskA, d.maskB};
+             d.C, d.ldc, nsplit > 1 ? scratch : nullptr, d.maskA, d.maskB, d.add_identity};
   dim3 grid((unsigned)tm, (unsigned)tn, (unsigned)nsplit);
   const double gbytes = 8.0 * ((double)d.M * d.K + (double)d.K * d.N +
                                (d.beta == 0.0 ? 1.0 : 2.0) * (double)d.M * d.N);
@@ -438,7 +439,7 @@ hipError_t gemm(const GemmDesc& d, hipStream_t s, double* scratch, int64_t scrat
     TimedLaunch tr(s, "gemm_splitk_reduce", 8.0 * (double)MN * (nsplit + 2), (double)MN * nsplit);
     const int blocks = (int)((MN + 63) / 64);
     hipLaunchKernelGGL(k_splitk_reduce, dim3(blocks), dim3(256), 0, s, (const double*)scratch,
-                       (int)nsplit, d.M, d.N, d.beta, d.C, d.ldc);
+                       (int)nsplit, d.M, d.N, d.beta, d.C, d.ldc, d.add_identity);
   }
   if (flops) *flops += 2.0 * (double)d.M * (double)d.N * (double)d.K;
   return hipGetLastError();

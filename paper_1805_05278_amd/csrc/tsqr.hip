@@ -427,13 +427,88 @@ __device__ __forceinline__ void hr_mm(double (*C)[kNB + 1], double (*A)[kNB + 1]
     for (int r = 0; r < 4; ++r) C[16 * w + lk + 4 * r][16 * ct + li] = acc[ct][r];
 }
 
+// One step j of the sign-modified LU (thread (i, p) holds X[i][p + 4m] in
+// xr[m] and L^{-1}[i][p + 4m] in er[m]); recurses over j so that the register
+// slot of column j, j / 4, is a constant.
+template <int J>
+__device__ __forceinline__ void hr_lu(double (&xr)[16], double (&er)[16], int i, int p, int nbr,
+                                      double (*Rb)[2][4][16], double* Sv, double* Ui) {
+  if constexpr (J < kNB) {
+    if (J < nbr) {
+      constexpr int slot = J & 1, q = J & 3, mj = J >> 2;
+      if (i == J) {
+        if (p == q) {
+          const double sg = (xr[mj] >= 0.0) ? 1.0 : -1.0;
+          xr[mj] += sg;
+          Sv[J] = sg;
+          Ui[J] = 1.0 / xr[mj];
+        }
+#pragma unroll
+        for (int m = 0; m < 16; m += 2) {
+          *(double2*)&Rb[slot][0][p][m] = make_double2(xr[m], xr[m + 1]);
+          *(double2*)&Rb[slot][1][p][m] = make_double2(er[m], er[m + 1]);
+        }
+      }
+      __syncthreads();
+      if (i > J && i < nbr) {
+        // Multiplier l = X[i][J] / U_JJ, formed by the thread holding column
+        // J and shared with the other three threads of the row.
+        double l = (p == q) ? xr[mj] * Ui[J] : 0.0;
+        l = dpp_mov<q | (q << 2) | (q << 4) | (q << 6)>(l);
+        if (p == q) xr[mj] = l;
+#pragma unroll
+        for (int m = 0; m < 16; m += 2) {
+          const double2 rx = *(const double2*)&Rb[slot][0][p][m];
+          const double2 re = *(const double2*)&Rb[slot][1][p][m];
+          const int k0 = p + 4 * m, k1 = k0 + 4;
+          xr[m] -= (k0 > J ? l : 0.0) * rx.x;
+          xr[m + 1] -= (k1 > J ? l : 0.0) * rx.y;
+          er[m] -= (k0 <= J ? l : 0.0) * re.x;
+          er[m + 1] -= (k1 <= J ? l : 0.0) * re.y;
+        }
+      }
+    }
+    hr_lu<J + 1>(xr, er, i, p, nbr, Rb, Sv, Ui);
+  }
+}
+
+// Backward elimination for U^{-1}, step J (descending): rows above J lose
+// U[i][J] / U_JJ times row J of the running inverse (mr).
+template <int J>
+__device__ __forceinline__ void hr_uinv(const double (&xr)[16], double (&mr)[16], int i, int p,
+                                        int nbr, double (*Rb)[2][4][16], const double* Ui) {
+  if constexpr (J >= 1) {
+    if (J < nbr) {
+      constexpr int slot = J & 1, q = J & 3, mj = J >> 2;
+      if (i == J) {
+#pragma unroll
+        for (int m = 0; m < 16; m += 2)
+          *(double2*)&Rb[slot][0][p][m] = make_double2(mr[m], mr[m + 1]);
+      }
+      __syncthreads();
+      if (i < J) {
+        double f = (p == q) ? xr[mj] * Ui[J] : 0.0;
+        f = dpp_mov<q | (q << 2) | (q << 4) | (q << 6)>(f);
+#pragma unroll
+        for (int m = 0; m < 16; m += 2) {
+          const double2 rm = *(const double2*)&Rb[slot][0][p][m];
+          const int k0 = p + 4 * m, k1 = k0 + 4;
+          mr[m] -= (k0 >= J ? f : 0.0) * rm.x;
+          mr[m + 1] -= (k1 >= J ? f : 0.0) * rm.y;
+        }
+      }
+    }
+    hr_uinv<J - 1>(xr, mr, i, p, nbr, Rb, Ui);
+  }
+}
+
 __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
   __shared__ double Bm[kNB][kNB + 1];
   __shared__ double Mm[kNB][kNB + 1];
   __shared__ double Xm[kNB][kNB + 1];
   __shared__ double Sm[kNB][kNB + 1];
   __shared__ double Sv[kNB], Dv[kNB], Ui[kNB];
-  __shared__ double pinv;
+  __shared__ __align__(16) double Rb[2][2][4][16];  // [slot][x / e][p][m]: the step's pivot row
   const int t = threadIdx.x;
   const int nbr = a.nbr;
   for (int i = t; i < kTS; i += 256) {
@@ -484,66 +559,33 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
   __syncthreads();
   // Sign-modified LU without pivoting (App. C.2): before eliminating column j,
   // S_jj = sgn(X^_jj) (+1 for >= 0) and X^_jj += S_jj.  The row operations are
-  // applied to the identity alongside, which therefore ends as L^{-1}.
-  const int i = t >> 2, p = t & 3;
-  for (int j = 0; j < nbr; ++j) {
-    if (t == 0) {
-      const double sg = (Xm[j][j] >= 0.0) ? 1.0 : -1.0;
-      Sv[j] = sg;
-      Xm[j][j] += sg;
-      pinv = 1.0 / Xm[j][j];
+  // applied to the identity alongside, which therefore ends as L^{-1}; then
+  // U^{-1} by backward elimination.  Thread (i, p) keeps row i's columns
+  // p, p + 4, ... in registers; hr_lu_step / hr_uinv_step are unrolled over
+  // the step index so that every register index is a constant.
+  {
+    const int i = t >> 2, p = t & 3;
+    double xr[16], er[16], mr[16];
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int k = p + 4 * m;
+      xr[m] = Xm[i][k];
+      er[m] = (i == k) ? 1.0 : 0.0;
+      mr[m] = (i == k) ? 1.0 : 0.0;
     }
     __syncthreads();
-    if (i > j && i < nbr) {
-      const double l = Xm[i][j] * pinv;
-      double xj[16], xi[16], ej[16], ei[16];
+    hr_lu<0>(xr, er, i, p, nbr, Rb, Sv, Ui);
+    hr_uinv<63>(xr, mr, i, p, nbr, Rb, Ui);
+    // Back to LDS for the products below: X (L below, U on and above the
+    // diagonal), L^{-1} in Bm, U^{-1} (rows scaled by 1/U_ii) in Mm.
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int k = j + 1 + p + 4 * m;
-        const bool ok = k < nbr;
-        xj[m] = ok ? Xm[j][k] : 0.0;
-        xi[m] = ok ? Xm[i][k] : 0.0;
-        const int ke = p + 4 * m;
-        ej[m] = (ke <= j) ? Bm[j][ke] : 0.0;
-        ei[m] = (ke <= j) ? Bm[i][ke] : 0.0;
-      }
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int k = j + 1 + p + 4 * m;
-        if (k < nbr) Xm[i][k] = xi[m] - l * xj[m];
-        const int ke = p + 4 * m;
-        if (ke <= j) Bm[i][ke] = ei[m] - l * ej[m];
-      }
-      if (p == 0) Xm[i][j] = l;
+    for (int m = 0; m < 16; ++m) {
+      const int k = p + 4 * m;
+      Xm[i][k] = xr[m];
+      Bm[i][k] = er[m];
+      Mm[i][k] = (i < nbr) ? mr[m] * Ui[i] : mr[m];
     }
     __syncthreads();
-  }
-  // U^{-1} by backward elimination on [U | I]: rows above j lose
-  // (U[i][j] / U[j][j]) times row j; the rows are scaled by 1/U_ii at the end.
-  if (t < nbr) Ui[t] = 1.0 / Xm[t][t];
-  __syncthreads();
-  for (int j = nbr - 1; j >= 1; --j) {
-    if (i < j) {
-      const double f = Xm[i][j] * Ui[j];
-      double fj[16], fi[16];
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int k = j + p + 4 * m;
-        const bool ok = k < nbr;
-        fj[m] = ok ? Mm[j][k] : 0.0;
-        fi[m] = ok ? Mm[i][k] : 0.0;
-      }
-#pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int k = j + p + 4 * m;
-        if (k < nbr) Mm[i][k] = fi[m] - f * fj[m];
-      }
-    }
-    __syncthreads();
-  }
-  for (int e = t; e < kTS; e += 256) {
-    const int r = e % kNB, cc = e / kNB;
-    if (r < nbr && cc < nbr) Mm[r][cc] *= Ui[r];
   }
   // R = -S R_root, optional D = sign(diag R).
   if (t < nbr) {
