@@ -185,9 +185,20 @@ def bench_mixed(torch, miqr, synth, h, m=65536, n=2048, cond=1e2, seed=34001):
             torch.cuda.synchronize()
             times.append(time.perf_counter() - t)
         best = min(times[1:])
+        # One more solve with per-kernel event timing (not part of the best time).
+        Ad.copy_(A0)
+        Bd.copy_(B0)
+        torch.cuda.synchronize()
+        h.profile(True)
+        h.lstsq(Ad, Bd, h.opts(precision=prec))
+        torch.cuda.synchronize()
+        tot = h.profile_totals()
+        h.profile(False)
         out[name] = {"ms": best * 1e3, "solves_per_s": 1.0 / best, "status": st,
                      "backward_error": info.backward_error, "iterations": info.iterations,
-                     "fallback": info.fallback}
+                     "fallback": info.fallback,
+                     "kernels_ms": {k: round(v["ms"], 3) for k, v in
+                                    sorted(tot.items(), key=lambda kv: -kv[1]["ms"])}}
     out["speedup_fp32_vs_fp64"] = out["fp64"]["ms"] / out["fp32"]["ms"]
     out["speedup_bf16_vs_fp64"] = out["fp64"]["ms"] / out["bf16"]["ms"]
     return out

@@ -23,10 +23,14 @@ using namespace miqr;
 
 
 namespace {
-// Points the launch-site timer at the handle for the duration of an entry point.
+// Points the launch-site timer at the handle for the duration of an entry
+// point.  It also clears the thread's last-error state first: hipGetLastError
+// reports the last failure of any runtime call on the thread, and the entry
+// point's launch checks must not pick up an unrelated earlier one.
 struct ProfScope {
   KernelTimer* prev;
   explicit ProfScope(miqr_handle h) : prev(g_timer) {
+    (void)hipGetLastError();
     g_timer = (h && h->profiling) ? &h->timer : nullptr;
   }
   ~ProfScope() { g_timer = prev; }
@@ -358,27 +362,33 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
                         qr_info* info) {
   const Tuning tune = tuning_from(o, m, n);
   FactorLayout L = factor_layout(m, n, tune);
-  const int64_t need = L.total + 2 * n * n + m * n + 3 * m * k + 7 * n * k + 8 * k + 64 * 16 + 256;
-  miqr_status st = ensure_ws(h, (size_t)need * sizeof(double));
+  MixedWs w;
+  // The workspace size is taken from the same carving that assigns the
+  // pointers (a dry run over a null base), so the two cannot disagree.
+  auto carve = [&](Arena& ar) {
+    ar.take(L.total);
+    w.T = ar.take(n * n);
+    w.Rinv = ar.take(n * n);
+    w.A0 = ar.take(m * n);
+    w.B0 = ar.take(m * k);
+    w.Rr = ar.take(m * k);
+    w.Qv = ar.take(m * k);
+    w.X = ar.take(n * k);
+    w.S = ar.take(n * k);
+    w.P = ar.take(n * k);
+    w.Tv = ar.take(n * k);
+    w.U = ar.take(n * k);
+    w.W1 = ar.take(n * k);
+    w.W2 = ar.take(n * k);
+    w.nrm = ar.take(4 * k + n + 8);
+    w.coef = ar.take(2 * k + 8);
+  };
+  Arena dry{nullptr};
+  carve(dry);
+  miqr_status st = ensure_ws(h, (size_t)dry.off * sizeof(double));
   if (st != MIQR_OK) return st;
   Arena ar{(double*)h->ws};
-  ar.take(L.total);
-  MixedWs w;
-  w.T = ar.take(n * n);
-  w.Rinv = ar.take(n * n);
-  w.A0 = ar.take(m * n);
-  w.B0 = ar.take(m * k);
-  w.Rr = ar.take(m * k);
-  w.Qv = ar.take(m * k);
-  w.X = ar.take(n * k);
-  w.S = ar.take(n * k);
-  w.P = ar.take(n * k);
-  w.Tv = ar.take(n * k);
-  w.U = ar.take(n * k);
-  w.W1 = ar.take(n * k);
-  w.W2 = ar.take(n * k);
-  w.nrm = ar.take(4 * k + n + 8);
-  w.coef = ar.take(2 * k + 8);
+  carve(ar);
   {
     Arena far{(double*)h->ws};
     far.take(L.tsqr);
@@ -391,13 +401,17 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
   const int maxit = 100;
   copy_matrix(s, m, n, A, lda, w.A0, m);
   copy_matrix(s, m, k, B, ldb, w.B0, m);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed copies");
   st = do_factor(h, s, m, n, A, lda, w.T, n, o, comp);
   if (st != MIQR_OK) return st;
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed factor");
   find_zero_diagonal(s, n, A, lda, h->dflag);
   int flag = 0;
-  hipError_t e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed");
+  if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed singularity check");
   bool converged = false;
   int iters = 0;
   double worst = 0.0;
@@ -504,7 +518,7 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
       xpby_cols(s, n, k, w.S, n, w.coef + k, w.P, n);
     }
   }
-  if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed");
+  if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed refinement");
   converged = !flag && worst <= tol;
   if (converged) {
     copy_matrix(s, n, k, w.X, n, B, ldb);
@@ -515,7 +529,7 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
       info->backward_error = worst;
     }
     e = hipGetLastError();
-    if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed");
+    if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed result");
     return MIQR_OK;
   }
   // Fallback: refactor the original in FP64.
@@ -822,19 +836,26 @@ miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t 
   // Layout: factorisation workspace first, then T, W1, W2, and (for info) copies.
   const Tuning tune = tuning_from(o, m, n);
   FactorLayout L = factor_layout(m, n, tune);
-  const int64_t extra = n * n + 2 * n * nrhs + (info ? (m * n + m * nrhs + 3 * nrhs + n + 64) : 0) + 256;
-  miqr_status st = ensure_ws(h, (size_t)(L.total + extra) * sizeof(double));
+  double *T = nullptr, *W1 = nullptr, *W2 = nullptr;
+  double *A0 = nullptr, *B0 = nullptr, *nrm = nullptr;
+  auto carve = [&](Arena& ar) {
+    ar.take(L.total);
+    T = ar.take(n * n);
+    W1 = ar.take(n * nrhs);
+    W2 = ar.take(n * nrhs);
+    if (info) {
+      A0 = ar.take(m * n);
+      B0 = ar.take(m * nrhs);
+      nrm = ar.take(3 * nrhs + n + 8);
+    }
+  };
+  Arena dry{nullptr};
+  carve(dry);
+  miqr_status st = ensure_ws(h, (size_t)dry.off * sizeof(double));
   if (st != MIQR_OK) return st;
   Arena ar{(double*)h->ws};
-  ar.take(L.total);
-  double* T = ar.take(n * n);
-  double* W1 = ar.take(n * nrhs);
-  double* W2 = ar.take(n * nrhs);
-  double *A0 = nullptr, *B0 = nullptr, *nrm = nullptr;
+  carve(ar);
   if (info) {
-    A0 = ar.take(m * n);
-    B0 = ar.take(m * nrhs);
-    nrm = ar.take(3 * nrhs + n + 8);
     copy_matrix(s, m, n, A, lda, A0, m);
     copy_matrix(s, m, nrhs, B, ldb, B0, m);
   }

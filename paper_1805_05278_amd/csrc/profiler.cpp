@@ -51,6 +51,7 @@ void KernelTimer::collect() {
     free_.push_back(p.b);
   }
   pending_.clear();
+  (void)hipGetLastError();  // a failed timing query must not surface elsewhere
 }
 
 void KernelTimer::clear() {

@@ -89,3 +89,23 @@ def test_mixed_factor_is_a_valid_qr_of_a_nearby_matrix(miqr, prec):
     ulow = {"fp32": 2.0 ** -24, "bf16": 2.0 ** -8}[prec]
     assert np.linalg.norm(Q.T @ Q - np.eye(300)) <= 1e-12
     assert np.linalg.norm(A - Q @ R) / np.linalg.norm(A) <= 50 * ulow
+
+
+def test_mixed_after_fp64_on_same_handle():
+    """An FP64 solve sizes the handle's workspace for itself; the mixed solve
+    that follows needs more and must size its own layout exactly (its norm
+    buffer once fell outside the allocation when n was large)."""
+    import paper_1805_05278_amd as m_
+    h = m_.Handle(0)
+    try:
+        A = synth.conditioned(8192, 2048, 1e2, 77)
+        _, B = synth.ls_rhs(A, 78, noise=1e-6, nrhs=1)
+        for prec in (m_.FP64, m_.MIXED_FP32, m_.MIXED_BF16):
+            Ad, Bd = m_.to_colmajor(A), m_.to_colmajor(B)
+            st, info = h.lstsq(Ad, Bd, h.opts(precision=prec))
+            torch.cuda.synchronize()
+            assert st in (m_.OK, m_.ENOCONV)
+            x = Bd.cpu().numpy()[:2048, 0]
+            assert oracle.backward_error(A, x, B[:, 0]) <= 1e-13
+    finally:
+        h.close()
