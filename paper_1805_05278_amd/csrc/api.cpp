@@ -159,6 +159,11 @@ struct EgCtx {
   int64_t ldq = 0;
   int normalize = 0;
   double* sign = nullptr;
+  // Least-squares use: leave the T12 blocks of the nodes on the recursion's
+  // right spine (root, root.right, ...) unassembled.  No trailing update
+  // needs them (a node's T is used only when it is a left half); Q^T b is
+  // then applied along the spine (apply_qt_spine).
+  bool skip_spine_t = false;
 };
 
 void run_gemm(EgCtx& e, const GemmDesc& d) {
@@ -168,7 +173,7 @@ void run_gemm(EgCtx& e, const GemmDesc& d) {
 
 // Alg. 2 (QR-EG) on the sub-problem with top-left corner (r0, c0), mk rows
 // (to the bottom of A) and nk columns.
-void eg(EgCtx& e, int64_t r0, int64_t c0, int64_t mk, int64_t nk) {
+void eg(EgCtx& e, int64_t r0, int64_t c0, int64_t mk, int64_t nk, bool spine = true) {
   if (e.err != hipSuccess) return;
   double* A = e.A;
   const int64_t lda = e.lda, ldt = e.ldt;
@@ -179,7 +184,7 @@ void eg(EgCtx& e, int64_t r0, int64_t c0, int64_t mk, int64_t nk) {
     return;
   }
   const int64_t n1 = split_point(nk, e.tune.b), n2 = nk - n1;
-  eg(e, r0, c0, mk, n1);
+  eg(e, r0, c0, mk, n1, false);
   double* VL = A + r0 + c0 * lda;
   double* C = A + r0 + (c0 + n1) * lda;
   double* TL = e.T + c0 + c0 * ldt;
@@ -202,7 +207,8 @@ void eg(EgCtx& e, int64_t r0, int64_t c0, int64_t mk, int64_t nk) {
   d.A = VL; d.lda = lda; d.maskA = MASK_UNIT_LOWER;
   d.B = e.Wb; d.ldb = n1; d.C = C; d.ldc = lda; d.compute = e.update_compute;
   run_gemm(e, d);
-  eg(e, r0 + n1, c0 + n1, mk - n1, n2);
+  eg(e, r0 + n1, c0 + n1, mk - n1, n2, spine);
+  if (spine && e.skip_spine_t) return;
   double* VR = A + (r0 + n1) + (c0 + n1) * lda;
   double* TR = e.T + (c0 + n1) + (c0 + n1) * ldt;
   // M3 = V_L^T [0; V_R] = V_L[n1:, :]^T V_R
@@ -228,7 +234,8 @@ void eg(EgCtx& e, int64_t r0, int64_t c0, int64_t mk, int64_t nk) {
 bool bad_ptr(const void* p) { return p == nullptr; }
 
 miqr_status do_factor(miqr_handle h, hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda,
-                      double* T, int64_t ldt, const qr_opts* o, int update_compute) {
+                      double* T, int64_t ldt, const qr_opts* o, int update_compute,
+                      bool skip_spine_t = false) {
   const Tuning tune = tuning_from(o, m, n);
   FactorLayout L = factor_layout(m, n, tune);
   miqr_status st = ensure_ws(h, (size_t)L.total * sizeof(double));
@@ -247,6 +254,7 @@ miqr_status do_factor(miqr_handle h, hipStream_t s, int64_t m, int64_t n, double
   e.scratch = ar.take(L.scratch);
   e.scratch_n = L.scratch;
   e.update_compute = update_compute;
+  e.skip_spine_t = skip_spine_t;
   // A single TSQR panel can emit Q and the normalised R itself, except for
   // square matrices whose last reflector is switched afterwards.
   const bool single = n <= tune.b && m > n;
@@ -300,6 +308,26 @@ miqr_status do_apply(miqr_handle h, hipStream_t s, char trans, int64_t m, int64_
   }
   if (e != hipSuccess) return hip_fail(h, e, "apply_q");
   return MIQR_OK;
+}
+
+// C <- Q^T C for factors whose right-spine T12 blocks were not assembled:
+// Q = Q_L Q_R at every spine node, so Q^T C applies (V_L, T_L)^T to the
+// node's rows and moves on to the right child, down to the last panel.
+miqr_status apply_qt_spine(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64_t k,
+                           const double* VR, int64_t lda, const double* T, int64_t ldt,
+                           double* C, int64_t ldc, int64_t b, double* W1, double* W2,
+                           double* scratch, int64_t scratch_n) {
+  int64_t r0 = 0, c0 = 0, mk = m, nk = n;
+  for (;;) {
+    const int64_t w = nk <= b ? nk : split_point(nk, b);
+    miqr_status st = do_apply(h, s, 'T', mk, w, k, VR + r0 + c0 * lda, lda, T + c0 + c0 * ldt,
+                              ldt, C + r0, ldc, W1, W2, scratch, scratch_n);
+    if (st != MIQR_OK || w == nk) return st;
+    r0 += w;
+    c0 += w;
+    mk -= w;
+    nk -= w;
+  }
 }
 
 // beta(x) = max_c ||A^T r_c|| / (||A||_F (||A||_F ||x_c|| + ||r_c||)),
@@ -403,7 +431,7 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
   copy_matrix(s, m, k, B, ldb, w.B0, m);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed copies");
-  st = do_factor(h, s, m, n, A, lda, w.T, n, o, comp);
+  st = do_factor(h, s, m, n, A, lda, w.T, n, o, comp, true);
   if (st != MIQR_OK) return st;
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed factor");
@@ -437,7 +465,8 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
     // x0 = R^{-1} (Q^T b)[0:n]
     copy_matrix(s, m, k, w.B0, m, w.Rr, m);
     if (e == hipSuccess) {
-      miqr_status s2 = do_apply(h, s, 'T', m, n, k, A, lda, w.T, n, w.Rr, m, w.W1, w.W2, w.sc, w.scn);
+      miqr_status s2 = apply_qt_spine(h, s, m, n, k, A, lda, w.T, n, w.Rr, m, tune.b, w.W1, w.W2,
+                                      w.sc, w.scn);
       if (s2 != MIQR_OK) return s2;
     }
     G('N', n, k, n, 1.0, w.Rinv, n, MASK_UPPER, w.Rr, m, 0.0, w.X, n);
@@ -555,9 +584,9 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
 miqr_status lstsq_fp64(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64_t k, double* A,
                        int64_t lda, double* B, int64_t ldb, const qr_opts* o, double* T,
                        double* W1, double* W2, double* sc, int64_t scn, qr_info* info) {
-  miqr_status st = do_factor(h, s, m, n, A, lda, T, n, o, COMPUTE_F64);
+  miqr_status st = do_factor(h, s, m, n, A, lda, T, n, o, COMPUTE_F64, true);
   if (st != MIQR_OK) return st;
-  st = do_apply(h, s, 'T', m, n, k, A, lda, T, n, B, ldb, W1, W2, sc, scn);
+  st = apply_qt_spine(h, s, m, n, k, A, lda, T, n, B, ldb, tuning_from(o, m, n).b, W1, W2, sc, scn);
   if (st != MIQR_OK) return st;
   find_zero_diagonal(s, n, A, lda, h->dflag);
   int flag = 0;
@@ -861,7 +890,7 @@ miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t 
   }
   // The factorisation uses the front of the workspace (do_factor re-derives
   // the same layout, so the regions above stay untouched).
-  st = do_factor(h, s, m, n, A, lda, T, n, o, COMPUTE_F64);
+  st = do_factor(h, s, m, n, A, lda, T, n, o, COMPUTE_F64, true);
   if (st != MIQR_OK) return st;
   // The factorisation's split-K scratch (same arena layout as do_factor) is free now.
   Arena far{(double*)h->ws};
@@ -869,7 +898,7 @@ miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t 
   far.take(L.wa);
   far.take(L.wb);
   double* sc = far.take(L.scratch);
-  st = do_apply(h, s, 'T', m, n, nrhs, A, lda, T, n, B, ldb, W1, W2, sc, L.scratch);
+  st = apply_qt_spine(h, s, m, n, nrhs, A, lda, T, n, B, ldb, tune.b, W1, W2, sc, L.scratch);
   if (st != MIQR_OK) return st;
   find_zero_diagonal(s, n, A, lda, h->dflag);
   int flag = 0;
