@@ -120,49 +120,107 @@ def bench_batched(torch, miqr, synth, h, count=10000, seed=4242):
             "kernel_frac_fp64_alu_peak": flops / (kms * 1e-3) / PEAK["fp64"] if kms == kms else None}
 
 
-def bench_serving(torch, miqr, synth, h, count=10000, qps=8000.0, seed=99):
-    """Open-loop Poisson stream through the serving loop: host (pinned) inputs,
-    arrival -> completion latency per request."""
+def bench_serving(torch, miqr, synth, h, count=10000, qps=4000.0, seed=99):
+    """Open-loop Poisson stream through the serving loop with pinned host
+    inputs: arrival -> completion latency at an offered rate the server
+    sustains, then capacity with every request submitted at once."""
     import numpy as np
-    trace = synth.serving_trace(count, qps, seed)
     P = 32
     g = torch.Generator().manual_seed(seed)
-    poolA = [torch.randn((256, 4096), generator=g, dtype=torch.float64).pin_memory().t()
+    # Each request's A (m x n) and B (m x nrhs) are contiguous column-major
+    # blocks (lda = m), as a client would send them: the leading m n values of
+    # a pooled pinned buffer.
+    poolA = [torch.randn(4096 * 256, generator=g, dtype=torch.float64).pin_memory()
              for _ in range(P)]
-    poolB = [torch.randn((4, 4096), generator=g, dtype=torch.float64).pin_memory().t()
+    poolB = [torch.randn(4096 * 4, generator=g, dtype=torch.float64).pin_memory()
              for _ in range(P)]
-    X = [np.zeros((r.n, r.nrhs), order="F") for r in trace]
-    srv = miqr.Server(h, hbm_budget=16 << 30, max_batch=1024)
-    # Warm the path (graphs, pools) with a few requests first.
-    warm = 8
-    for i in range(warm):
-        r = trace[i]
-        srv.submit(poolA[i % P][:r.m, :r.n], poolB[i % P][:r.m, :r.nrhs], X[i])
-    got = 0
-    while got < warm:
-        got += len(srv.poll(wait=True))
-    recs = []
-    t0 = srv.clock()
-    idx = 0
-    while len(recs) < count:
-        now = srv.clock() - t0
-        if now > 300.0:
-            raise RuntimeError("serving run did not finish (%d of %d done)" % (len(recs), count))
-        while idx < count and trace[idx].arrival_s <= now:
-            r = trace[idx]
-            srv.submit(poolA[idx % P][:r.m, :r.n], poolB[idx % P][:r.m, :r.nrhs], X[idx])
-            idx += 1
-        recs.extend(srv.poll())
-    srv.close()
-    lat = np.array([d["end_s"] - d["submit_s"] for d in recs])
-    span = max(d["end_s"] for d in recs) - min(d["submit_s"] for d in recs)
+
+    def req_views(i, r):
+        a = poolA[i % P][: r.m * r.n].view(r.n, r.m).t()
+        b = poolB[i % P][: r.m * r.nrhs].view(r.nrhs, r.m).t()
+        return a, b
+
+    def run(rate):
+        trace = synth.serving_trace(count, rate, seed)
+        X = [np.zeros((r.n, r.nrhs), order="F") for r in trace]
+        srv = miqr.Server(h, hbm_budget=16 << 30, max_batch=1024)
+        # Warm the path (graphs, pools) with a few requests first.
+        warm = 8
+        for i in range(warm):
+            srv.submit(*req_views(i, trace[i]), X[i])
+        got = 0
+        while got < warm:
+            got += len(srv.poll(wait=True))
+        recs = []
+        t0 = srv.clock()
+        idx = 0
+        while len(recs) < count:
+            now = srv.clock() - t0
+            if now > 300.0:
+                raise RuntimeError("serving run did not finish (%d of %d done)" % (len(recs), count))
+            while idx < count and trace[idx].arrival_s <= now:
+                srv.submit(*req_views(idx, trace[idx]), X[idx])
+                idx += 1
+            recs.extend(srv.poll())
+        srv.close()
+        lat = np.array([d["end_s"] - d["submit_s"] for d in recs])
+        span = max(d["end_s"] for d in recs) - min(d["submit_s"] for d in recs)
+        return trace, recs, lat, span
+
+    trace, recs, lat, span = run(qps)
     flops = sum(nominal_ls_flops(r.m, r.n, r.nrhs) for r in trace)
     h2d = sum(8.0 * r.m * (r.n + r.nrhs) for r in trace)
-    return {"requests": count, "qps_offered": qps, "solves_per_s": count / span,
-            "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_batch": float(np.mean([d["batch_size"] for d in recs])),
-            "gflops_nominal": flops / span / 1e9, "h2d_gb": h2d / 1e9,
-            "inputs": "pinned host memory (32 pooled 4096x256 N(0,1) matrices, leading m x n blocks)"}
+    out = {"requests": count, "qps_offered": qps, "solves_per_s": count / span,
+           "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
+           "mean_batch": float(np.mean([d["batch_size"] for d in recs])),
+           "gflops_nominal": flops / span / 1e9, "h2d_gb": h2d / 1e9,
+           "inputs": "pinned host memory: each request's A and B contiguous (lda = m), "
+                     "taken from 32 pooled N(0,1) buffers"}
+    _, recs2, lat2, span2 = run(0.0)
+    out["capacity"] = {"solves_per_s": count / span2, "h2d_gb_per_s": h2d / span2 / 1e9,
+                       "p50_ms": float(np.percentile(lat2, 50) * 1e3),
+                       "p99_ms": float(np.percentile(lat2, 99) * 1e3),
+                       "mean_batch": float(np.mean([d["batch_size"] for d in recs2])),
+                       "note": "all requests submitted at t = 0"}
+    return out
+
+
+def bench_eg(torch, miqr, synth, h, shapes=((16384, 16384), (65536, 8192)), reps=3):
+    """Square and moderately tall recursive EG QR (FP64): QR GFLOP/s per shape,
+    inputs resident, best of `reps` after one warm-up, with the GEMMs' share."""
+    out = {}
+    for (m, n) in shapes:
+        A0 = synth.gaussian_device(m, n, 31000 + n)
+        T = miqr.colmajor(n, n)
+        A = miqr.colmajor(m, n)
+        best, tot = None, None
+        for r in range(reps + 1):
+            A.copy_(A0)
+            torch.cuda.synchronize()
+            if r == reps:
+                h.profile(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            h.factor(A, T)
+            e1.record()
+            torch.cuda.synchronize()
+            if r == reps:
+                tot = h.profile_totals()
+                h.profile(False)
+            elif r > 0:
+                ms = e0.elapsed_time(e1)
+                best = ms if best is None else min(best, ms)
+        gemm_ms = sum(v["ms"] for k, v in tot.items() if k.startswith("gemm"))
+        gemm_fl = sum(v["flops"] for k, v in tot.items() if k.startswith("gemm"))
+        out["%dx%d" % (m, n)] = {
+            "ms": best, "gflops_nominal": nominal_flops(m, n) / (best * 1e-3) / 1e9,
+            "frac_fp64_peak": nominal_flops(m, n) / (best * 1e-3) / PEAK["fp64"],
+            "gemm_tflops": gemm_fl / (gemm_ms * 1e-3) / 1e12 if gemm_ms else None,
+            "gemm_share": gemm_ms / sum(v["ms"] for v in tot.values()),
+            "algorithmic_gemm_flops": gemm_fl}
+        del A0, A, T
+        torch.cuda.empty_cache()
+    return out
 
 
 def bench_mixed(torch, miqr, synth, h, m=65536, n=2048, cond=1e2, seed=34001):
@@ -371,8 +429,8 @@ def main():
                                "launches_per_step": v["launches"] / args.steps}
                            for k, v in sorted(totals.items(), key=lambda kv: -kv[1]["ms"])}
     if not args.no_extras:
-        for key, fn in (("batched", bench_batched), ("serving", bench_serving),
-                        ("mixed_ls", bench_mixed)):
+        for key, fn in (("eg_square_tall", bench_eg), ("batched", bench_batched),
+                        ("serving", bench_serving), ("mixed_ls", bench_mixed)):
             try:
                 line[key] = fn(torch, miqr, synth, h)
             except Exception as exc:  # reported, never hidden
