@@ -38,6 +38,14 @@
 
 namespace miqr {
 
+// A copy of v that the compiler cannot merge with other uses of v: index
+// arithmetic built on it is recomputed where it is used instead of being kept
+// live (and spilled) across the kernel.
+__device__ __forceinline__ int fresh_copy(int v) {
+  asm volatile("" : "+v"(v));
+  return v;
+}
+
 struct ChainQRArgs {
   double* X;       // leaf level: panel (in place); tree level: child R array
   int64_t ldx;
@@ -83,9 +91,11 @@ struct Lay {
 //   first:  plain Householder QR of the rows themselves (pivot row j);
 //   !first: the rows are stacked under the upper triangular R held in Rs.
 // On return x holds the basis (rows below the pivot for `first`, all rows
-// otherwise), Rs the new R (for !first), Gs the kernel T in its upper
-// triangle (Gs must be zero below the diagonal and outside nbr on entry), and
-// taus the reflector scalars.
+// otherwise), Rs the new R (for !first), Gs the Gram entries v_i . v_j in its
+// strict upper triangle (Gs must be zero below the diagonal and outside nbr on
+// entry), and taus the reflector scalars; build_t then turns Gs into T.  The
+// two are separate so that a caller can store x first and build T without
+// the block's registers live.
 template <int H, bool first>
 __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
                                         double (*Rs)[kNB + 1], double (*Gs)[kNB + 1],
@@ -179,7 +189,12 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
     }
   }
   __syncthreads();
+}
 
+// T in place of the Gram entries left by qr_step.
+__device__ __forceinline__ void build_t(double (*Gs)[kNB + 1], const double* taus, double* Wt,
+                                        int nbr) {
+  const int t = threadIdx.x;
   // T from the Gram entries G (strict upper part of Gs) and tau (Sec. 2.3:
   // T^{-1} = striu(V^T V) + diag(tau)^{-1}), built blockwise in place: first
   // the 8 x 8 diagonal blocks by the column recurrence
@@ -200,7 +215,7 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
   }
   for (int sz = 8; sz < kNB; sz *= 2) {
     const int npair = kNB / (2 * sz);
-    for (int e = t; e < npair * sz * sz; e += 512) {
+    for (int e = fresh_copy(t); e < npair * sz * sz; e += 512) {
       const int pr = e / (sz * sz), i = (e / sz) % sz, k = e % sz;
       const int a = 2 * sz * pr, b = a + sz;
       double s = 0.0;
@@ -208,7 +223,7 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
       Wt[e] = s;
     }
     __syncthreads();
-    for (int e = t; e < npair * sz * sz; e += 512) {
+    for (int e = fresh_copy(t); e < npair * sz * sz; e += 512) {
       const int pr = e / (sz * sz), i = (e / sz) % sz, k = e % sz;
       const int a = 2 * sz * pr, b = a + sz;
       double s = 0.0;
@@ -238,7 +253,7 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
   __shared__ double taus[kNB];
   __shared__ double Wt[32 * kNB / 2];
 
-  for (int i = t; i < kTS; i += 512) {
+  for (int i = fresh_copy(t); i < kTS; i += 512) {
     const int r = i % kNB, cc = i / kNB;
     double v = 0.0;
     if (!LEAF && r < nbr && cc < nbr) v = a.X[(int64_t)b0 * kTS + i];
@@ -278,9 +293,10 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
         for (int s = 0; s < 8; ++s)
           if (c < nbr && 8 * rg + s < rows) src[s + (int64_t)c * ld] = x[u][s];
       }
+      build_t(Gs, taus, Wt, nbr);
       double* Tb = a.T + (int64_t)b * kTS;
       if (!first) {
-        for (int i = t; i < kTS; i += 512) {
+        for (int i = fresh_copy(t); i < kTS; i += 512) {
           const int r = i % kNB, cc = i / kNB;
           Tb[i] = (r <= cc && cc < nbr) ? Gs[r][cc] : 0.0;
         }
@@ -299,7 +315,7 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
           }
         }
         __syncthreads();
-        for (int i = t; i < kTS; i += 512) {
+        for (int i = fresh_copy(t); i < kTS; i += 512) {
           const int r = i % kNB, cc = i / kNB;
           double z = 0.0;
           if (r <= cc && cc < nbr)
@@ -350,18 +366,19 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
         if (c < nbr && r < rows) Yn[r + c * kYL] = x[u][s];
       }
     }
+    build_t(Gs, taus, Wt, nbr);
     double* Tn = a.T + (int64_t)chain * kTS;
-    for (int i = t; i < kTS; i += 512) {
+    for (int i = fresh_copy(t); i < kTS; i += 512) {
       const int r = i % kNB, cc = i / kNB;
       Tn[i] = (r <= cc && cc < nbr) ? Gs[r][cc] : 0.0;
     }
     __syncthreads();
   } else {
     double* Tn = a.T + (int64_t)chain * kTS;
-    for (int i = t; i < kTS; i += 512) Tn[i] = 0.0;
+    for (int i = fresh_copy(t); i < kTS; i += 512) Tn[i] = 0.0;
   }
 
-  for (int i = t; i < kTS; i += 512) {
+  for (int i = fresh_copy(t); i < kTS; i += 512) {
     const int r = i % kNB, cc = i / kNB;
     a.R[(int64_t)chain * kTS + i] = (r <= cc && cc < nbr) ? Rs[r][cc] : 0.0;
   }

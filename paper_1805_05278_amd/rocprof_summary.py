@@ -54,11 +54,27 @@ def library_name(symbol: str) -> str:
     return ""
 
 
-def source_digest() -> str:
-    """Digest of the HIP/C++ sources; a traffic record is valid only for the
-    sources it was measured on."""
+# Library kernel name prefix -> the source files its code and launch shapes
+# come from. A kernel's traffic record is valid only for those sources.
+_KERNEL_SOURCES = [
+    ("gemm_", ("gemm.hip", "gemm.h", "common.h")),
+    ("tsqr_", ("tsqr.hip", "tsqr.h", "common.h")),
+    ("batched_ls", ("batched.hip", "batched.h", "common.h")),
+    ("trsm_diag", ("solve.hip", "solve.h", "common.h")),
+]
+
+
+def source_digest(kernel: str = "") -> str:
+    """Digest of the sources a kernel is built from (all HIP/C++ sources when
+    the kernel is not named or not known)."""
+    files = None
+    for prefix, names in _KERNEL_SOURCES:
+        if kernel.startswith(prefix):
+            files = [os.path.join(HERE, "csrc", n) for n in names]
+    if files is None:
+        files = sorted(glob.glob(os.path.join(HERE, "csrc", "*")))
     h = hashlib.sha256()
-    for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+    for p in files:
         with open(p, "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -141,7 +157,7 @@ def traffic(args):
         lines.append("| %s | %d | %.1f | %.1f | %.3f |" % (k, len(fe[k]), f, w, b / 1e6))
         if k != "copy_calibration":
             out[k] = {"hbm_bytes_per_launch": b, "fetch_kib": f, "write_kib": w,
-                      "dispatches": len(fe[k]), "source_digest": digest}
+                      "dispatches": len(fe[k]), "source_digest": source_digest(k)}
     lines += ["", "source digest: %s" % digest, ""]
     with open(args.out, "w") as fo:
         fo.write("\n".join(lines))
