@@ -400,13 +400,21 @@ hipError_t gemm(const GemmDesc& d, hipStream_t s, double* scratch, int64_t scrat
     // a K = 0 product only happens for empty panels, which callers avoid.
     return hipSuccess;
   }
-  const bool big = d.M >= 128 && d.N >= 128;
+  // 128 x 128 tiles when there are enough of them to fill the chip, or when
+  // a long K (split below) supplies the parallelism and the larger tile
+  // halves the operand re-reads; 64 x 64 tiles otherwise.
+  const int64_t t128 = ((d.M + 127) / 128) * ((d.N + 127) / 128);
+  const bool big = d.M >= 128 && d.N >= 128 && (t128 >= 128 || d.K >= 4096);
   const int BM = big ? 128 : 64, BN = big ? 128 : 64;
   const int64_t tm = (d.M + BM - 1) / BM, tn = (d.N + BN - 1) / BN;
   const int64_t tiles = tm * tn;
+  // Split-K when the output has few tiles: slices of at least 512 for long K,
+  // of at least 32 for short K (the small products of a recursion node, whose
+  // one or few workgroups would otherwise walk K alone).
   int64_t nsplit = 1;
-  if (tiles < 512 && d.K >= 1024 && scratch && scratch_doubles >= 2 * d.M * d.N) {
-    nsplit = std::min<int64_t>((1024 + tiles - 1) / tiles, d.K / 512);
+  const int64_t min_chunk = d.K >= 1024 ? 512 : 32;
+  if (tiles < 512 && d.K >= 2 * min_chunk && scratch && scratch_doubles >= 2 * d.M * d.N) {
+    nsplit = std::min<int64_t>((1024 + tiles - 1) / tiles, d.K / min_chunk);
     nsplit = std::min<int64_t>(nsplit, scratch_doubles / (d.M * d.N));
     nsplit = std::max<int64_t>(nsplit, 1);
   }
