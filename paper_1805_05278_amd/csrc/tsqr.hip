@@ -102,6 +102,10 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
                                         double (*vbuf)[H], double* taus, double* Wt) {
   constexpr int RG = Lay<H>::RG, CPT = Lay<H>::CPT;
   const int t = threadIdx.x, rg = t % RG, cg = t / RG;
+  // The reflector is posted to vb with rows (8 rg + s, 8 rg + s + 1) as the
+  // pair rg of slice s / 2, so that consecutive lanes read consecutive 16-byte
+  // pairs (a row-major layout would put the lanes 64 bytes apart and on
+  // conflicting banks).
   // Columns are taken CPT at a time so that the owner's register slot U is a
   // compile-time index (a runtime slot would force x out of registers).
   for (int j0 = 0; j0 < nbr; j0 += CPT) {
@@ -146,7 +150,7 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
         }
 #pragma unroll
         for (int s = 0; s < 8; s += 2)
-          *(double2*)&vb[8 * rg + s] = make_double2(nv[s], nv[s + 1]);
+          *(double2*)&vb[s * RG + 2 * rg] = make_double2(nv[s], nv[s + 1]);
         if (rg == 0) {
           taus[j] = tau;
           if (!first) Rs[j][j] = beta;
@@ -156,7 +160,7 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
       double v[8];
 #pragma unroll
       for (int s = 0; s < 8; s += 2) {
-        const double2 p = *(const double2*)&vb[8 * rg + s];
+        const double2 p = *(const double2*)&vb[s * RG + 2 * rg];
         v[s] = p.x;
         v[s + 1] = p.y;
       }
