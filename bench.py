@@ -11,10 +11,12 @@ factorisations are independent and run on two streams with a handle each
 (--serial: one stream, one after the other).
 
 value = nominal QR flops (2 m n^2 - 2 n^3 / 3, summed over both matrices) per
-second.  The JSON line also carries the roofline of the dominant kernel
-(per-launch algorithmic bytes or flops over its average duration, from HIP
-events recorded around every library launch inside the timed region) and the
-CPU oracle timed on a bounded sample of the same workload.
+second, from a timed region of K steps with no instrumentation.  A second
+timed region of K more steps records HIP events around every library launch
+(on the stream it runs on); the roofline of the dominant kernel (per-launch
+algorithmic bytes or flops over its average duration) comes from those.  The
+JSON line also carries the CPU oracle timed on a bounded sample of the same
+workload.
 """
 import argparse
 import json
@@ -337,8 +339,12 @@ def main():
         step(*work)
         torch.cuda.synchronize()
     def measure(streams):
-        """Time args.steps steps on `streams`; returns (ms per step, wall s,
-        per-kernel totals, last step's outputs)."""
+        """Time args.steps steps on `streams`, then (unless --no-profile) the
+        same number of steps again with an event pair around every kernel.
+        Returns (ms per step of the clean pass, its wall s, per-kernel totals
+        of the instrumented pass, ms per step of the instrumented pass, last
+        step's outputs).  The per-kernel events add a gap between launches, so
+        the step time is taken from the pass without them."""
         def step(As, b):
             with torch.cuda.stream(streams[0]):
                 h1.factor(As[0], Ts[0], opts[0])
@@ -347,37 +353,44 @@ def main():
                 h.apply_q("T", As[1], Ts[1], b)
                 h.solve_r(As[1], b[:n2])
 
-        batches = [fresh() for _ in range(args.steps)]
-        torch.cuda.synchronize()
-        if not args.no_profile:
-            h1.profile(True)
-            h.profile(True)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        main = torch.cuda.current_stream()
-        t0 = time.perf_counter()
-        e0.record(main)
-        for st in streams:
-            st.wait_stream(main)
-        for As, b in batches:
-            step(As, b)
-        for st in streams:
-            main.wait_stream(st)
-        e1.record(main)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        totals = {}
-        if not args.no_profile:
-            for hh in (h1, h):
-                for k, v in hh.profile_totals().items():
-                    t = totals.setdefault(k, dict(ms=0.0, launches=0, bytes=0.0, flops=0.0))
-                    for f in t:
-                        t[f] += v[f]
-        h1.profile(False)
-        h.profile(False)
-        return e0.elapsed_time(e1) / args.steps, wall, totals, batches[-1]
+        def timed(profiled):
+            batches = [fresh() for _ in range(args.steps)]
+            torch.cuda.synchronize()
+            if profiled:
+                h1.profile(True)
+                h.profile(True)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            main = torch.cuda.current_stream()
+            t0 = time.perf_counter()
+            e0.record(main)
+            for st in streams:
+                st.wait_stream(main)
+            for As, b in batches:
+                step(As, b)
+            for st in streams:
+                main.wait_stream(st)
+            e1.record(main)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            totals = {}
+            if profiled:
+                for hh in (h1, h):
+                    for k, v in hh.profile_totals().items():
+                        t = totals.setdefault(k, dict(ms=0.0, launches=0, bytes=0.0, flops=0.0))
+                        for f in t:
+                            t[f] += v[f]
+                h1.profile(False)
+                h.profile(False)
+            return e0.elapsed_time(e1) / args.steps, wall, totals, batches[-1]
 
-    ms, wall, totals, last = measure(streams)
+        ms, wall, _, last = timed(False)
+        totals, pms = {}, None
+        if not args.no_profile:
+            pms, _, totals, _ = timed(True)
+        return ms, wall, totals, pms, last
+
+    ms, wall, totals, pms, last = measure(streams)
     serial = None
     if not args.serial:
         one = torch.cuda.current_stream()
@@ -418,15 +431,17 @@ def main():
                                "plus one least-squares RHS on the 262144x256 factors",
                    "streams": 1 if args.serial else 2,
                    "fraction_of_fp64_peak": value * 1e9 / PEAK["fp64"],
-                   "wall_s": wall, "recon_err_top4096": rec},
+                   "wall_s": wall, "recon_err_top4096": rec,
+                   "ms_per_step_with_kernel_events": pms},
     }
     # The dominant kernel is the one with the most time in the one-stream step,
     # where launches do not share the chip; on two streams overlapping launches
     # stretch each other's durations and the ranking of close kernels can flip.
     dom = None
     if serial is not None:
-        sms, swall, stot, _ = serial
+        sms, swall, stot, spms, _ = serial
         line["serial"] = {"ms_per_step": sms, "value": flops / (sms * 1e-3) / 1e9,
+                          "ms_per_step_with_kernel_events": spms,
                           "note": "same step on one stream, the two factorisations in turn"}
         if stot:
             dom = dominant(stot)

@@ -818,10 +818,11 @@ TsqrPlan tsqr_plan(int64_t rows, int nbr, int leaf_rows, int chain, int arity, d
   if (leaf_rows != 128 && leaf_rows != 256) leaf_rows = (rows >= 256 * 64) ? 256 : 128;
   p.leaf_rows = leaf_rows;
   const int64_t P0 = std::max<int64_t>(1, (rows + leaf_rows - 1) / leaf_rows);
-  // Chains of up to four blocks once there are enough blocks to keep every
-  // CU busy (measured best for 2^18..2^20 rows; longer chains starve the
-  // second leaf launch of workgroups).
-  if (chain <= 0) chain = (int)std::max<int64_t>(1, std::min<int64_t>(4, P0 / 256));
+  // Chains long enough to leave about 512 of them (two workgroups per CU for
+  // the stacked-block launch), at most eight blocks: measured best at 2^18
+  // rows (chain 2) and 2^20 rows (chain 8).  Longer chains starve that launch
+  // of workgroups; shorter ones add tree levels.
+  if (chain <= 0) chain = (int)std::max<int64_t>(1, std::min<int64_t>(8, P0 / 512));
   // A node stacks arity - 1 child R factors (nbr rows each) in kYL rows.
   const int max_arity = 1 + kYL / std::max(nbr, 1);
   if (arity < 2) arity = std::min(max_arity, 5);
