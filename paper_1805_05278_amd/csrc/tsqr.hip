@@ -195,47 +195,82 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
   __syncthreads();
 }
 
-// T in place of the Gram entries left by qr_step.
+// One pairing level of build_t: for each pair of diagonal blocks of size SZ,
+// T12 = -T1 (G12 T2).  The sums run over whole block rows / columns: the
+// entries outside a triangle are zero in Gs, so no bounds are needed and the
+// loads of a sum can all be in flight together.
+template <int SZ>
+__device__ __forceinline__ void t_pair_level(double (*Gs)[kNB + 1], double* Wt) {
+  constexpr int NP = kNB / (2 * SZ);
+  const int t = threadIdx.x;
+  for (int e = fresh_copy(t); e < NP * SZ * SZ; e += 512) {
+    const int pr = e / (SZ * SZ), i = (e / SZ) % SZ, k = e % SZ;
+    const int a = 2 * SZ * pr, b = a + SZ;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int m = 0; m < SZ; m += 2) {
+      s0 += Gs[a + i][b + m] * Gs[b + m][b + k];
+      s1 += Gs[a + i][b + m + 1] * Gs[b + m + 1][b + k];
+    }
+    Wt[e] = s0 + s1;
+  }
+  __syncthreads();
+  for (int e = fresh_copy(t); e < NP * SZ * SZ; e += 512) {
+    const int pr = e / (SZ * SZ), i = (e / SZ) % SZ, k = e % SZ;
+    const int a = 2 * SZ * pr, b = a + SZ;
+    const double* w = Wt + pr * SZ * SZ + k;
+    double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+    for (int m = 0; m < SZ; m += 2) {
+      s0 += Gs[a + i][a + m] * w[m * SZ];
+      s1 += Gs[a + i][a + m + 1] * w[(m + 1) * SZ];
+    }
+    Gs[a + i][b + k] = -(s0 + s1);
+  }
+  __syncthreads();
+}
+
+// T from its 16 x 16 diagonal blocks (in place in Gs) and the Gram entries
+// above them: blocks of 16 and 32 are paired, T12 = -T1 (G12 T2).
+__device__ __forceinline__ void t_from_blocks(double (*Gs)[kNB + 1], double* Wt) {
+  t_pair_level<16>(Gs, Wt);
+  t_pair_level<32>(Gs, Wt);
+}
+
+// T in place of the Gram entries left by qr_step (Gs zero below the
+// diagonal and outside nbr).
 __device__ __forceinline__ void build_t(double (*Gs)[kNB + 1], const double* taus, double* Wt,
                                         int nbr) {
   const int t = threadIdx.x;
   // T from the Gram entries G (strict upper part of Gs) and tau (Sec. 2.3:
   // T^{-1} = striu(V^T V) + diag(tau)^{-1}), built blockwise in place: first
   // the 8 x 8 diagonal blocks by the column recurrence
-  // T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j], then blocks of 8, 16, 32 are
-  // paired, T12 = -T1 (G12 T2).
-  if (t < kNB) Gs[t][t] = (t < nbr) ? taus[t] : 0.0;
+  // T[0:j, j] = -tau_j T[0:j, 0:j] G[0:j, j], taken row by row (row i needs
+  // only its own earlier entries, so each thread builds one row alone), then
+  // blocks of 8, 16, 32 are paired, T12 = -T1 (G12 T2).
+  double Tr[8];
+  const int bb = t >> 3, i = t & 7, r0 = 8 * bb;
+  if (t < kNB) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const int col = r0 + j;
+      const double tj = (col < nbr) ? taus[col] : 0.0;
+      double sacc = 0.0;
+#pragma unroll
+      for (int k = 0; k < j; ++k) sacc += Tr[k] * Gs[r0 + k][col];
+      Tr[j] = (i == j) ? tj : ((i < j) ? -tj * sacc : 0.0);
+    }
+  }
   __syncthreads();
-  for (int jj = 1; jj < 8; ++jj) {
-    const int bb = t >> 3, i = t & 7;
-    const int col = 8 * bb + jj, row = 8 * bb + i;
-    const bool act = t < kNB && i < jj && col < nbr;
-    double s = 0.0;
-    if (act)
-      for (int k = i; k < jj; ++k) s += Gs[row][8 * bb + k] * Gs[8 * bb + k][col];
-    __syncthreads();
-    if (act) Gs[row][col] = -taus[col] * s;
-    __syncthreads();
+  if (t < kNB) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j)
+      if (j >= i) Gs[r0 + i][r0 + j] = Tr[j];
   }
-  for (int sz = 8; sz < kNB; sz *= 2) {
-    const int npair = kNB / (2 * sz);
-    for (int e = fresh_copy(t); e < npair * sz * sz; e += 512) {
-      const int pr = e / (sz * sz), i = (e / sz) % sz, k = e % sz;
-      const int a = 2 * sz * pr, b = a + sz;
-      double s = 0.0;
-      for (int m = 0; m <= k; ++m) s += Gs[a + i][b + m] * Gs[b + m][b + k];
-      Wt[e] = s;
-    }
-    __syncthreads();
-    for (int e = fresh_copy(t); e < npair * sz * sz; e += 512) {
-      const int pr = e / (sz * sz), i = (e / sz) % sz, k = e % sz;
-      const int a = 2 * sz * pr, b = a + sz;
-      double s = 0.0;
-      for (int m = i; m < sz; ++m) s += Gs[a + i][a + m] * Wt[pr * sz * sz + m * sz + k];
-      Gs[a + i][b + k] = -s;
-    }
-    __syncthreads();
-  }
+  __syncthreads();
+  t_pair_level<8>(Gs, Wt);
+  t_pair_level<16>(Gs, Wt);
+  t_pair_level<32>(Gs, Wt);
 }
 
 // LEAF: the chain walks row blocks of the panel (else stacked child R's).
@@ -388,12 +423,525 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
   }
 }
 
-template <int H, bool LEAF, int PART>
-__global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
-  chain_qr_body<H, LEAF, PART>(a);
+// ------------------------------------------------ blocked block QR on MFMA
+//
+// For blocks of 256 rows the column-by-column step above spends most of its
+// issue slots on 32-lane reductions: every reflector is applied to all 64
+// columns at once.  The blocked form (the compact-WY recursion of Sec. 2.3
+// applied inside the block) factors 16-column sub-panels column by column,
+// each column held by half a wave (8 rows per lane, one reduction per
+// column), and applies each sub-panel to the columns right of it with two
+// FP64 MFMA products:  W = V_b^T X,  W' = T_b^T W,  X -= V_b W'.  The same
+// W product, taken over the columns left of the sub-panel too, yields the
+// Gram entries V^T V from which the block's T is built.
+//
+// Register layout ("tile layout"): wave w holds column tile ct = w / 2 and
+// row tiles 8 (w % 2) .. 8 (w % 2) + 7 of the 256 x 64 block; lane (g, cl)
+// (g = l / 16, cl = l % 16) holds rows g + 4 r (r = 0..3) of each 16 x 16
+// tile in column cl, which is the MFMA accumulator layout.  Global rows are
+// staged through the sub-panel buffer P, which also carries each sub-panel
+// between the tile layout and the column-step layout (thread t: column
+// t / 32, rows 8 (t % 32) .. + 7).
+
+constexpr int kPLD = 258;  // column stride of P (doubles)
+
+// Position of row r of a 256-row column in P: rows 8 q + s go to pair q of
+// slice s / 2, so that lanes reading 8 consecutive rows as four pairs hit
+// consecutive 16-byte words.
+__device__ __forceinline__ int ppos(int r) {
+  return ((r & 7) >> 1) * 64 + 2 * (r >> 3) + (r & 1);
 }
 
-// Blocks after the first of each leaf chain, at two workgroups per CU.
+struct MfmaQRShared {
+  double P[16][kPLD];        // one 256 x 16 column tile
+  double Wred[8][16][17];    // per-wave partial W tiles (also build_t's scratch)
+  double W[16][kNB + 1];     // W = V_b^T [R; X] of the sub-panel, trailing columns
+  double Wp[16][kNB + 1];    // W' = T_b^T W
+  double Tsub[16][17];
+  __align__(16) double vbuf[2][256];
+};
+
+// Tile-layout coordinates of thread t.
+struct TileCoord {
+  int w, g, cl, ct, rt0;
+  __device__ TileCoord(int t) {
+    w = t >> 6;
+    const int l = t & 63;
+    g = l >> 4;
+    cl = l & 15;
+    ct = w >> 1;
+    rt0 = (w & 1) * 8;
+  }
+  __device__ int row(int k, int r) const { return 16 * (rt0 + k) + g + 4 * r; }
+};
+
+// ppos(16 m + x) = ppos(x) + 4 m for x < 16: a tile's rows sit at a fixed
+// pattern plus 4 per tile, so the k loops below address P as one base per r
+// plus an immediate offset (instead of 32 live addresses).
+__device__ __forceinline__ int tile_base(const TileCoord& tc, int r) {
+  return tc.cl * kPLD + ppos(fresh_copy(tc.g) + 4 * r) + 4 * tc.rt0;
+}
+
+// Move column tile ct_ between the column-step layout in P and the tile
+// registers of its two owner waves.
+__device__ __forceinline__ void tiles_to_p(const TileCoord& tc, int ct_, const double (&xt)[8][4],
+                                           MfmaQRShared& S) {
+  if (tc.ct == ct_)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      double* p = &S.P[0][0] + tile_base(tc, r);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) p[4 * k] = xt[k][r];
+    }
+}
+__device__ __forceinline__ void p_to_tiles(const TileCoord& tc, int ct_, double (&xt)[8][4],
+                                           const MfmaQRShared& S) {
+  if (tc.ct == ct_)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const double* p = &S.P[0][0] + tile_base(tc, r);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) xt[k][r] = p[4 * k];
+    }
+}
+
+// Column-step layout: thread t holds rows 8 q .. 8 q + 7 (q = t % 32) of
+// column t / 32 of P.
+__device__ __forceinline__ void p_read8(const MfmaQRShared& S, int c, int q, double (&v)[8]) {
+#pragma unroll
+  for (int s = 0; s < 8; s += 2) {
+    const double2 p = *(const double2*)&S.P[c][(s >> 1) * 64 + 2 * q];
+    v[s] = p.x;
+    v[s + 1] = p.y;
+  }
+}
+__device__ __forceinline__ void p_write8(MfmaQRShared& S, int c, int q, const double (&v)[8]) {
+#pragma unroll
+  for (int s = 0; s < 8; s += 2)
+    *(double2*)&S.P[c][(s >> 1) * 64 + 2 * q] = make_double2(v[s], v[s + 1]);
+}
+
+// Load a 256 x 64 block into the tile registers; at(row, col) gives the
+// global element (rows < nrows and cols < nbr only; the rest reads 0).  All
+// global loads are issued before the first exchange through P.
+template <typename At>
+__device__ __forceinline__ void load_block(const TileCoord& tc, double (&xt)[8][4], int nrows,
+                                           int nbr, MfmaQRShared& S, At at) {
+  // Thread (c, q) moves rows q + 32 s of column c: a half-wave covers 32
+  // consecutive rows, so the global accesses coalesce.
+  const int t = threadIdx.x, c = t >> 5, q = t & 31;
+  double v[4][8];
+#pragma unroll
+  for (int ct_ = 0; ct_ < 4; ++ct_) {
+    const int col = 16 * ct_ + c;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int row = q + 32 * s;
+      v[ct_][s] = (col < nbr && row < nrows) ? at(row, col) : 0.0;
+    }
+  }
+#pragma unroll
+  for (int ct_ = 0; ct_ < 4; ++ct_) {
+#pragma unroll
+    for (int s = 0; s < 8; ++s) S.P[c][ppos(q + 32 * s)] = v[ct_][s];
+    __syncthreads();
+    p_to_tiles(tc, ct_, xt, S);
+    __syncthreads();
+  }
+}
+
+// Store the tile registers; put(row, col, value) for rows < nrows, cols < nbr.
+// The global stores are issued after the last exchange through P, so that no
+// barrier waits for them.
+template <typename Put>
+__device__ __forceinline__ void store_block(const TileCoord& tc, const double (&xt)[8][4],
+                                            int nrows, int nbr, MfmaQRShared& S, Put put) {
+  const int t = threadIdx.x, c = t >> 5, q = t & 31;
+  double v[4][8];
+#pragma unroll
+  for (int ct_ = 0; ct_ < 4; ++ct_) {
+    tiles_to_p(tc, ct_, xt, S);
+    __syncthreads();
+#pragma unroll
+    for (int s = 0; s < 8; ++s) v[ct_][s] = S.P[c][ppos(q + 32 * s)];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ct_ = 0; ct_ < 4; ++ct_) {
+    const int col = 16 * ct_ + c;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) {
+      const int row = q + 32 * s;
+      if (col < nbr && row < nrows) put(row, col, v[ct_][s]);
+    }
+  }
+}
+
+// Sum over the 32 lanes of a half-wave, result in every lane: the 16-lane
+// sums of group_sum, then the two rows exchanged in registers by
+// v_permlane16_swap (one copy ends up holding the even row in both rows, the
+// other the odd row) instead of a ds_swizzle round trip through the LDS unit.
+__device__ __forceinline__ double half_wave_sum(double v) {
+  v = group_sum<16>(v);
+  const unsigned long long u = (unsigned long long)__double_as_longlong(v);
+  const unsigned lo = (unsigned)(u & 0xffffffffull), hi = (unsigned)(u >> 32);
+  const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+  const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+  const double e =
+      __longlong_as_double((long long)(((unsigned long long)h[0] << 32) | (unsigned long long)l[0]));
+  const double o =
+      __longlong_as_double((long long)(((unsigned long long)h[1] << 32) | (unsigned long long)l[1]));
+  return e + o;
+}
+
+// Column jp of T_b (Sec. 2.3 recurrence, T[0:jp, jp] = -tau_jp T[0:jp, 0:jp]
+// G[0:jp, jp]), entry of row i.  Row i of T_b was cleared at the start of the
+// sub-panel, so the sum can run over all 16 terms: T[i][k] is zero for k < i
+// and for k >= jp (not built yet), and G is zero below its diagonal, where
+// only zero T entries meet it.  No bounds, so the loads overlap.
+__device__ __forceinline__ void tsub_column(MfmaQRShared& S, double (*Gs)[kNB + 1],
+                                            const double* taus, int b, int jp, int i) {
+  if (jp < 0) return;
+  const int jv = 16 * b + jp;
+  const double tj = taus[jv];
+  double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; k += 2) {
+    p0 += S.Tsub[i][k] * Gs[16 * b + k][jv];
+    p1 += S.Tsub[i][k + 1] * Gs[16 * b + k + 1][jv];
+  }
+  S.Tsub[i][jp] = (i == jp) ? tj : ((i < jp) ? -tj * (p0 + p1) : 0.0);
+}
+
+// Blocked Householder QR of the block in xt (first: the rows themselves;
+// else stacked under the upper triangular R in Rs).  On return xt holds the
+// basis (first: R on and above the diagonal of the top rows), Rs the new R
+// (stacked), Gs the Gram entries v_i . v_j (i < j) in its strict upper part,
+// taus the reflector scalars.  Gs must be zero elsewhere, taus zero beyond
+// nbr.
+template <bool first>
+__device__ void mfma_block_qr(const TileCoord& tc, double (&xt)[8][4], int nbr,
+                              double (*Rs)[kNB + 1], double (*Gs)[kNB + 1], double* taus,
+                              MfmaQRShared& S) {
+  const int t = threadIdx.x, c = t >> 5, q = t & 31;
+  const int nsub = (nbr + 15) >> 4;
+  for (int b = 0; b < nsub; ++b) {
+    // Sub-panel b into the column-step layout; T_b cleared (its rows are
+    // built during the column steps).
+    tiles_to_p(tc, b, xt, S);
+    if (t < 16 * 17) (&S.Tsub[0][0])[t] = 0.0;
+    __syncthreads();
+    const int jc = 16 * b + c;
+    double xf[8];
+    p_read8(S, c, q, xf);
+    for (int j = 0; j < 16; ++j) {
+      const int jg = 16 * b + j;
+      if (jg >= nbr) break;
+      double* vb = S.vbuf[j & 1];
+      if (c == j) {
+        double s4[4] = {0.0, 0.0, 0.0, 0.0}, av = 0.0;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int r = 8 * q + s;
+          if (first) {
+            s4[s & 3] += (r > jg) ? xf[s] * xf[s] : 0.0;
+            av = (r == jg) ? xf[s] : av;
+          } else {
+            s4[s & 3] += xf[s] * xf[s];
+          }
+        }
+        const double ss = half_wave_sum((s4[0] + s4[1]) + (s4[2] + s4[3]));
+        const double alpha = first ? half_wave_sum(av) : Rs[jg][jg];
+        double beta = alpha, tau = 0.0, scale = 1.0;
+        if (ss != 0.0) {
+          const double nrm = sqrt(alpha * alpha + ss);
+          beta = (alpha >= 0.0) ? -nrm : nrm;
+          tau = (beta - alpha) / beta;
+          scale = 1.0 / (alpha - beta);
+        }
+        double nv[8];
+#pragma unroll
+        for (int s = 0; s < 8; ++s) {
+          const int r = 8 * q + s;
+          const double sc = xf[s] * scale;
+          if (first) {
+            nv[s] = (r > jg) ? sc : ((r == jg) ? 1.0 : 0.0);
+            xf[s] = (r > jg) ? sc : ((r == jg) ? beta : xf[s]);
+          } else {
+            nv[s] = sc;
+            xf[s] = sc;
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < 8; s += 2)
+          *(double2*)&vb[(s >> 1) * 64 + 2 * q] = make_double2(nv[s], nv[s + 1]);
+        if (q == 0) {
+          taus[jg] = tau;
+          if (!first) Rs[jg][jg] = beta;
+        }
+      }
+      __syncthreads();
+      if (c > j && jc < nbr) {
+        double v[8];
+#pragma unroll
+        for (int s = 0; s < 8; s += 2) {
+          const double2 p = *(const double2*)&vb[(s >> 1) * 64 + 2 * q];
+          v[s] = p.x;
+          v[s + 1] = p.y;
+        }
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int s = 0; s < 8; s += 2) {
+          a0 += v[s] * xf[s];
+          a1 += v[s + 1] * xf[s + 1];
+        }
+        const double d = half_wave_sum(a0 + a1);
+        const double wv = taus[jg] * (first ? d : d + Rs[jg][jc]);
+#pragma unroll
+        for (int s = 0; s < 8; ++s) xf[s] -= v[s] * wv;
+        if (!first && q == 0) Rs[jg][jc] -= wv;
+      } else if (c < j) {
+        // Columns left of the pivot are final: their half-waves form the
+        // Gram entries v_c . v_j (v_j is zero above its pivot row, where a
+        // first block's column still holds R), and half-wave 0 builds
+        // column j - 1 of T_b, whose Gram column is complete.
+        double v[8];
+#pragma unroll
+        for (int s = 0; s < 8; s += 2) {
+          const double2 p = *(const double2*)&vb[(s >> 1) * 64 + 2 * q];
+          v[s] = p.x;
+          v[s + 1] = p.y;
+        }
+        double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+        for (int s = 0; s < 8; s += 2) {
+          a0 += v[s] * xf[s];
+          a1 += v[s + 1] * xf[s + 1];
+        }
+        const double d = half_wave_sum(a0 + a1);
+        if (q == 0) Gs[jc][jg] = d;
+        if (c == 0 && q < 16) tsub_column(S, Gs, taus, b, j - 1, q);
+      }
+    }
+    // The factored sub-panel back into P and into its owners' tiles.
+    p_write8(S, c, q, xf);
+    __syncthreads();
+    p_to_tiles(tc, b, xt, S);
+    if (t < 16) tsub_column(S, Gs, taus, b, min(16, nbr - 16 * b) - 1, t);
+
+    // Partial W = V_b^T X over this wave's 128 rows, all column tiles (the
+    // tiles left of b and b itself give Gram entries, the rest the update).
+    // MFMA operands: A = V_b^T (lane: V_b[row][16 b + cl]), B = X (lane:
+    // xt[k][r]); the k index of the product runs over rows g + 4 r.
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+    if (16 * tc.ct < nbr) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const double* pv = &S.P[0][0] + tile_base(tc, r);
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+          double av = pv[4 * k];
+          double bx = xt[k][r];
+          if (first) {
+            const int row = tc.row(k, r);
+            const int vc = 16 * b + tc.cl, xc = 16 * tc.ct + tc.cl;
+            av = (row < vc) ? 0.0 : ((row == vc) ? 1.0 : av);
+            if (tc.ct <= b) bx = (row < xc) ? 0.0 : ((row == xc) ? 1.0 : bx);
+          }
+          acc = mfma64(av, bx, acc);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < 4; ++r) S.Wred[tc.w][tc.g + 4 * r][tc.cl] = acc[r];
+    __syncthreads();
+    for (int e = fresh_copy(t); e < 16 * kNB; e += 512) {
+      const int m = e & 15, col = e >> 4, ct_ = col >> 4, n = col & 15;
+      const int jv = 16 * b + m;
+      const double val = S.Wred[2 * ct_][m][n] + S.Wred[2 * ct_ + 1][m][n];
+      if (ct_ < b) {
+        if (jv < nbr) Gs[col][jv] = val;
+      } else if (ct_ > b) {
+        S.W[m][col] = val + ((first || jv >= nbr || col >= nbr) ? 0.0 : Rs[jv][col]);
+      }
+    }
+    // T_b into the diagonal block of Gs (its Gram entries are used up).
+    if (t < 256) {
+      const int i = t >> 4, jj = t & 15;
+      if (i <= jj) Gs[16 * b + i][16 * b + jj] = S.Tsub[i][jj];
+    }
+    __syncthreads();
+    if (16 * (b + 1) >= nbr) continue;  // no columns right of the last sub-panel
+    // W' = T_b^T W on the trailing columns; R rows of the sub-panel (stacked).
+    for (int e = fresh_copy(t); e < 16 * kNB; e += 512) {
+      const int m = e & 15, col = e >> 4;
+      if (col < 16 * (b + 1)) continue;
+      double sacc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 16; ++k) sacc += S.Tsub[k][m] * S.W[k][col];  // T_b upper: 0 for k > m
+      S.Wp[m][col] = sacc;
+      if (!first && 16 * b + m < nbr && col < nbr) Rs[16 * b + m][col] -= sacc;
+    }
+    __syncthreads();
+    // X -= V_b W' on the column tiles right of b.  A = V_b (lane: V_b[row
+    // 16 (rt0 + k) + cl][16 b + 4 p + g]), B = W' (lane: W'[4 p + g][16 ct + cl]).
+    if (tc.ct > b && 16 * tc.ct < nbr) {
+      // Row 16 (rt0 + k) + cl of column 4 p + g of P sits at
+      // pa + 4 k + 4 p kPLD; W'[4 p + g][16 ct + cl] at pw + 4 p (kNB + 1).
+      const double* pa = &S.P[0][0] + fresh_copy(tc.g) * kPLD + ppos(tc.cl) + 4 * tc.rt0;
+      const double* pw = &S.Wp[0][0] + fresh_copy(tc.g) * (kNB + 1) + 16 * tc.ct + tc.cl;
+      double wp[4];
+#pragma unroll
+      for (int p = 0; p < 4; ++p) wp[p] = -pw[4 * p * (kNB + 1)];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        d4 xa = d4{xt[k][0], xt[k][1], xt[k][2], xt[k][3]};
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+          double av = pa[4 * k + 4 * p * kPLD];
+          if (first) {
+            const int row = 16 * (tc.rt0 + k) + tc.cl, vc = 16 * b + 4 * p + tc.g;
+            av = (row < vc) ? 0.0 : ((row == vc) ? 1.0 : av);
+          }
+          xa = mfma64(av, wp[p], xa);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xt[k][r] = xa[r];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Chain / node body for 256-row blocks on the blocked MFMA factorisation
+// (same roles of LEAF and PART as chain_qr_body).
+template <bool LEAF, int PART>
+__device__ __forceinline__ void chain_qr_body_mfma(const ChainQRArgs& a) {
+  const int t = threadIdx.x;
+  const TileCoord tc(t);
+  const int chain = blockIdx.x;
+  const int b0 = chain * a.chain_len;
+  const int b1 = min(b0 + a.chain_len, a.nblocks);
+  const int nbr = a.nbr;
+  __shared__ double Rs[kNB][kNB + 1];
+  __shared__ double Gs[kNB][kNB + 1];
+  __shared__ double taus[kNB];
+  __shared__ MfmaQRShared S;
+  double* Wt = &S.Wred[0][0][0];
+
+  for (int i = fresh_copy(t); i < kTS; i += 512) {
+    const int r = i % kNB, cc = i / kNB;
+    double v = 0.0;
+    if (!LEAF && r < nbr && cc < nbr) v = a.X[(int64_t)b0 * kTS + i];
+    if (LEAF && PART == 2 && r <= cc && cc < nbr) v = a.R[(int64_t)chain * kTS + i];
+    Rs[r][cc] = v;
+    Gs[r][cc] = 0.0;
+  }
+  if (t < kNB) taus[t] = 0.0;
+  __syncthreads();
+
+  double xt[8][4];
+  if constexpr (LEAF) {
+    const int bs = PART == 2 ? b0 + 1 : b0;
+    const int be = PART == 1 ? b0 + 1 : b1;
+    for (int b = bs; b < be; ++b) {
+      const bool first = b == b0;
+      const int64_t rstart = ((int64_t)b * a.xrows) / a.nblocks;
+      const int rows = (int)((((int64_t)b + 1) * a.xrows) / a.nblocks - rstart);
+      double* src = a.X + rstart;
+      const int64_t ld = a.ldx;
+      load_block(tc, xt, rows, nbr, S,
+                 [&](int row, int col) { return src[row + (int64_t)col * ld]; });
+      if constexpr (PART != 2) {
+        if (first) mfma_block_qr<true>(tc, xt, nbr, Rs, Gs, taus, S);
+      }
+      if constexpr (PART != 1) {
+        if (!first) mfma_block_qr<false>(tc, xt, nbr, Rs, Gs, taus, S);
+      }
+      store_block(tc, xt, rows, nbr, S,
+                  [&](int row, int col, double v) { src[row + (int64_t)col * ld] = v; });
+      t_from_blocks(Gs, Wt);
+      double* Tb = a.T + (int64_t)b * kTS;
+      if (!first) {
+        for (int i = fresh_copy(t); i < kTS; i += 512) {
+          const int r = i % kNB, cc = i / kNB;
+          Tb[i] = (r <= cc && cc < nbr) ? Gs[r][cc] : 0.0;
+        }
+      } else if (PART != 2) {
+        // Z = T V_top^T (upper triangular) in place of T; Rs holds V_top
+        // (unit lower top nbr x nbr part of the block's basis) meanwhile.
+        if (tc.rt0 == 0) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = tc.row(k, r), col = 16 * tc.ct + tc.cl;
+              Rs[row][col] = (row > col) ? xt[k][r] : ((row == col) ? 1.0 : 0.0);
+            }
+        }
+        __syncthreads();
+        for (int i = fresh_copy(t); i < kTS; i += 512) {
+          const int r = i % kNB, cc = i / kNB;
+          double z = 0.0;
+          if (r <= cc && cc < nbr)
+            for (int k = r; k <= cc; ++k) z += Gs[r][k] * Rs[cc][k];
+          Tb[i] = z;
+        }
+        __syncthreads();
+        // The block's R (upper triangle of its top rows) seeds the chain.
+        if (tc.rt0 == 0) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = tc.row(k, r), col = 16 * tc.ct + tc.cl;
+              Rs[row][col] = (row <= col && col < nbr) ? xt[k][r] : 0.0;
+            }
+        }
+      }
+      __syncthreads();
+    }
+  } else if (b1 - b0 >= 2) {
+    // Tree node: children b0+1 .. b1-1 stacked (row stride nbr) under R_{b0}.
+    const int rows = (b1 - b0 - 1) * nbr;
+    const double* X = a.X;
+    load_block(tc, xt, rows, nbr, S, [&](int row, int col) {
+      const int sidx = row / nbr, rr = row - sidx * nbr;
+      return X[(int64_t)(b0 + 1 + sidx) * kTS + rr + col * kNB];
+    });
+    mfma_block_qr<false>(tc, xt, nbr, Rs, Gs, taus, S);
+    double* Yn = a.Y + (int64_t)chain * kYS;
+    store_block(tc, xt, rows, nbr, S,
+                [&](int row, int col, double v) { Yn[row + col * kYL] = v; });
+    t_from_blocks(Gs, Wt);
+    double* Tn = a.T + (int64_t)chain * kTS;
+    for (int i = fresh_copy(t); i < kTS; i += 512) {
+      const int r = i % kNB, cc = i / kNB;
+      Tn[i] = (r <= cc && cc < nbr) ? Gs[r][cc] : 0.0;
+    }
+    __syncthreads();
+  } else {
+    double* Tn = a.T + (int64_t)chain * kTS;
+    for (int i = fresh_copy(t); i < kTS; i += 512) Tn[i] = 0.0;
+  }
+
+  for (int i = fresh_copy(t); i < kTS; i += 512) {
+    const int r = i % kNB, cc = i / kNB;
+    a.R[(int64_t)chain * kTS + i] = (r <= cc && cc < nbr) ? Rs[r][cc] : 0.0;
+  }
+}
+
+template <int H, bool LEAF, int PART>
+__global__ __launch_bounds__(512) void k_chain_qr(ChainQRArgs a) {
+  if constexpr (H == 256) chain_qr_body_mfma<LEAF, PART>(a);
+  else chain_qr_body<H, LEAF, PART>(a);
+}
+
+// Blocks after the first of each leaf chain, at two workgroups per CU.  This
+// launch has enough chains to fill the chip twice over, so it keeps the
+// column-by-column body, which fits two workgroups per CU; the blocked body
+// needs 140 KB of LDS (one workgroup per CU) and only pays off where a CU has
+// one workgroup anyway (tree nodes, first blocks).
 template <int H>
 __global__ __launch_bounds__(512, 4) void k_chain_qr_rest(ChainQRArgs a) {
   chain_qr_body<H, true, 2>(a);

@@ -31,6 +31,7 @@ COPY_BYTES = 8.0 * (1 << 27)
 
 # Demangled kernel symbol -> the name the library's event timer uses.
 _PATTERNS = [
+    (r"k_chain_qr<\d+, true, 2>", "tsqr_chain_qr_leaf_rest"),
     (r"k_chain_qr<\d+, true, \d+>", "tsqr_chain_qr_leaf"),
     (r"k_chain_qr_rest<\d+>", "tsqr_chain_qr_leaf_rest"),
     (r"k_chain_qr<\d+, false, \d+>", "tsqr_chain_qr_tree"),
