@@ -95,39 +95,37 @@ struct SliceLoader {
       step = BK;
     }
   }
-  // Fast path: every element in range, no structure.
-  __device__ void load_fast(double (&r)[L]) const {
-#pragma unroll
-    for (int s = 0; s < L; ++s) r[s] = p[s * estride];
-  }
-  // General path: bounds (x < X, kk < kend) and structure mask on the stored
-  // (row, col) = along_i ? (x, kk) : (kk, x).
-  __device__ void load_checked(double (&r)[L], int64_t x0, int64_t X, int64_t k0, int64_t kend,
-                               int mask) const {
+  // Issue the slice's loads.  Elements out of range read `safe` (a valid
+  // address) instead; store() zeroes them and applies the structure mask.
+  // No branch selects between loaded values here, so the loads stay in
+  // flight across the MFMAs of the current slice.
+  __device__ void load(double (&r)[L], bool plain, const double* safe, int64_t x0, int64_t X,
+                       int64_t k0, int64_t kend) const {
 #pragma unroll
     for (int s = 0; s < L; ++s) {
       const int64_t x = x0 + i + s * di, kk = k0 + k + s * dk;
-      double v = 0.0;
-      if (x < X && kk < kend) {
-        v = p[s * estride];
+      const bool ok = plain || (x < X && kk < kend);
+      r[s] = *(ok ? p + s * estride : safe);
+    }
+  }
+  // Store a loaded slice: out-of-range elements become 0, the structure
+  // mask is applied on the stored (row, col) = along_i ? (x, kk) : (kk, x).
+  template <typename T, int LD, bool TRANS>
+  __device__ void store_masked(T (*S)[LD], const double (&r)[L], bool plain, int64_t x0, int64_t X,
+                               int64_t k0, int64_t kend, int mask) const {
+#pragma unroll
+    for (int s = 0; s < L; ++s) {
+      double v = r[s];
+      if (!plain) {
+        const int64_t x = x0 + i + s * di, kk = k0 + k + s * dk;
         const int64_t row = ALONG_I ? x : kk, col = ALONG_I ? kk : x;
         if (mask == MASK_UNIT_LOWER) v = (row < col) ? 0.0 : ((row == col) ? 1.0 : v);
         else if (mask == MASK_UPPER) v = (row > col) ? 0.0 : v;
+        v = (x < X && kk < kend) ? v : 0.0;  // after the mask: no unit diagonal outside
       }
-      r[s] = v;
+      if (TRANS) S[i + s * di][k + s * dk] = (T)v;
+      else S[k + s * dk][i + s * di] = (T)v;
     }
-  }
-  template <typename T, int LD>
-  __device__ void store(T (*S)[LD], const double (&r)[L]) const {
-#pragma unroll
-    for (int s = 0; s < L; ++s) S[k + s * dk][i + s * di] = (T)r[s];
-  }
-  // i-major store (S[i][k]), used for BF16 tiles whose MFMA fragments are
-  // 8 consecutive k values.
-  template <typename T, int LD>
-  __device__ void store_t(T (*S)[LD], const double (&r)[L]) const {
-#pragma unroll
-    for (int s = 0; s < L; ++s) S[i + s * di][k + s * dk] = (T)r[s];
   }
   __device__ void advance() { p += step; }
 };
@@ -182,19 +180,22 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   la.init(g.A, g.lda, i0, kbeg, t);
   lb.init(g.B, g.ldb, j0, kbeg, t);
   double ra[LA_t::L], rb[LB_t::L];
+  int64_t kf = kbeg;  // first k of the slice held in ra / rb
+  bool pa = true, pb = true;
   auto fetch = [&](int64_t k0) {
-    if (slice_is_plain<BM, BK, A_ALONG>(i0, g.M, k0, kend, g.maskA)) la.load_fast(ra);
-    else la.load_checked(ra, i0, g.M, k0, kend, g.maskA);
-    if (slice_is_plain<BN, BK, B_ALONG>(j0, g.N, k0, kend, g.maskB)) lb.load_fast(rb);
-    else lb.load_checked(rb, j0, g.N, k0, kend, g.maskB);
+    kf = k0;
+    pa = slice_is_plain<BM, BK, A_ALONG>(i0, g.M, k0, kend, g.maskA);
+    pb = slice_is_plain<BN, BK, B_ALONG>(j0, g.N, k0, kend, g.maskB);
+    la.load(ra, pa, g.A, i0, g.M, k0, kend);
+    lb.load(rb, pb, g.B, j0, g.N, k0, kend);
     la.advance();
     lb.advance();
   };
 
   if (nslab > 0) {
     fetch(kbeg);
-    la.store(As[0], ra);
-    lb.store(Bs[0], rb);
+    la.template store_masked<T, BM + PAD, false>(As[0], ra, pa, i0, g.M, kf, kend, g.maskA);
+    lb.template store_masked<T, BN + PAD, false>(Bs[0], rb, pb, j0, g.N, kf, kend, g.maskB);
   }
   __syncthreads();
   for (int it = 0; it < nslab; ++it) {
@@ -214,8 +215,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         for (int b = 0; b < SB; ++b) acc[a][b] = Tr::mma(bf[b], af[a], acc[a][b]);
     }
     if (more) {
-      la.store(As[cur ^ 1], ra);
-      lb.store(Bs[cur ^ 1], rb);
+      la.template store_masked<T, BM + PAD, false>(As[cur ^ 1], ra, pa, i0, g.M, kf, kend, g.maskA);
+      lb.template store_masked<T, BN + PAD, false>(Bs[cur ^ 1], rb, pb, j0, g.N, kf, kend, g.maskB);
     }
     __syncthreads();
   }
@@ -279,18 +280,21 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   la.init(g.A, g.lda, i0, kbeg, t);
   lb.init(g.B, g.ldb, j0, kbeg, t);
   double ra[LA_t::L], rb[LB_t::L];
+  int64_t kf = kbeg;  // first k of the slice held in ra / rb
+  bool pa = true, pb = true;
   auto fetch = [&](int64_t k0) {
-    if (slice_is_plain<BM, BK, A_ALONG>(i0, g.M, k0, kend, g.maskA)) la.load_fast(ra);
-    else la.load_checked(ra, i0, g.M, k0, kend, g.maskA);
-    if (slice_is_plain<BN, BK, B_ALONG>(j0, g.N, k0, kend, g.maskB)) lb.load_fast(rb);
-    else lb.load_checked(rb, j0, g.N, k0, kend, g.maskB);
+    kf = k0;
+    pa = slice_is_plain<BM, BK, A_ALONG>(i0, g.M, k0, kend, g.maskA);
+    pb = slice_is_plain<BN, BK, B_ALONG>(j0, g.N, k0, kend, g.maskB);
+    la.load(ra, pa, g.A, i0, g.M, k0, kend);
+    lb.load(rb, pb, g.B, j0, g.N, k0, kend);
     la.advance();
     lb.advance();
   };
   if (nslab > 0) {
     fetch(kbeg);
-    la.store_t(As[0], ra);
-    lb.store_t(Bs[0], rb);
+    la.template store_masked<__bf16, KP, true>(As[0], ra, pa, i0, g.M, kf, kend, g.maskA);
+    lb.template store_masked<__bf16, KP, true>(Bs[0], rb, pb, j0, g.N, kf, kend, g.maskB);
   }
   __syncthreads();
   for (int it = 0; it < nslab; ++it) {
@@ -308,8 +312,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       for (int b = 0; b < SB; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[b], af[a], acc[a][b], 0, 0, 0);
     if (more) {
-      la.store_t(As[cur ^ 1], ra);
-      lb.store_t(Bs[cur ^ 1], rb);
+      la.template store_masked<__bf16, KP, true>(As[cur ^ 1], ra, pa, i0, g.M, kf, kend, g.maskA);
+      lb.template store_masked<__bf16, KP, true>(Bs[cur ^ 1], rb, pb, j0, g.N, kf, kend, g.maskB);
     }
     __syncthreads();
   }
