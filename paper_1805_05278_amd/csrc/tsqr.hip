@@ -230,11 +230,43 @@ __device__ __forceinline__ void t_pair_level(double (*Gs)[kNB + 1], double* Wt) 
   __syncthreads();
 }
 
+// The same pairing level on FP64 MFMA (SZ = 16 or 32): the two products are
+// (SZ / 16)^2 output tiles per pair, one wave per tile, SZ / 4 k-steps each.
+// Operand layout: a = A[l % 16][l / 16], b = B[l / 16][l % 16],
+// acc[r] = D[l / 16 + 4 r][l % 16].
+template <int SZ>
+__device__ __forceinline__ void t_pair_level_mfma(double (*Gs)[kNB + 1], double* Wt) {
+  constexpr int NP = kNB / (2 * SZ), TPS = SZ / 16, NT = NP * TPS * TPS;
+  static_assert(NT <= 8, "one tile per wave");
+  const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
+  const int pr = w / (TPS * TPS), ti = (w / TPS) % TPS, tj = w % TPS;
+  const int a = 2 * SZ * pr, b = a + SZ;
+  double* Wp = Wt + pr * SZ * SZ;  // Wt[pr] as SZ x SZ, row-major
+  if (w < NT) {
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < SZ / 4; ++ks)
+      acc = mfma64(Gs[a + 16 * ti + li][b + 4 * ks + lk], Gs[b + 4 * ks + lk][b + 16 * tj + li], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Wp[(16 * ti + lk + 4 * r) * SZ + 16 * tj + li] = acc[r];
+  }
+  __syncthreads();
+  if (w < NT) {
+    d4 acc = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ks = 0; ks < SZ / 4; ++ks)
+      acc = mfma64(Gs[a + 16 * ti + li][a + 4 * ks + lk], Wp[(4 * ks + lk) * SZ + 16 * tj + li], acc);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) Gs[a + 16 * ti + lk + 4 * r][b + 16 * tj + li] = -acc[r];
+  }
+  __syncthreads();
+}
+
 // T from its 16 x 16 diagonal blocks (in place in Gs) and the Gram entries
 // above them: blocks of 16 and 32 are paired, T12 = -T1 (G12 T2).
 __device__ __forceinline__ void t_from_blocks(double (*Gs)[kNB + 1], double* Wt) {
-  t_pair_level<16>(Gs, Wt);
-  t_pair_level<32>(Gs, Wt);
+  t_pair_level_mfma<16>(Gs, Wt);
+  t_pair_level_mfma<32>(Gs, Wt);
 }
 
 // T in place of the Gram entries left by qr_step (Gs zero below the
@@ -268,6 +300,8 @@ __device__ __forceinline__ void build_t(double (*Gs)[kNB + 1], const double* tau
       if (j >= i) Gs[r0 + i][r0 + j] = Tr[j];
   }
   __syncthreads();
+  // VALU pairing: the two-workgroups-per-CU leaf kernel that uses this has
+  // no registers to spare for the MFMA form (t_from_blocks).
   t_pair_level<8>(Gs, Wt);
   t_pair_level<16>(Gs, Wt);
   t_pair_level<32>(Gs, Wt);
@@ -905,8 +939,11 @@ __device__ __forceinline__ void chain_qr_body_mfma(const ChainQRArgs& a) {
     // Tree node: children b0+1 .. b1-1 stacked (row stride nbr) under R_{b0}.
     const int rows = (b1 - b0 - 1) * nbr;
     const double* X = a.X;
+    // Child index of a stacked row by a float reciprocal: (row + 1/2) / nbr
+    // is never within 1/(2 nbr) of an integer, far above float rounding.
+    const float inv_nbr = 1.0f / (float)nbr;
     load_block(tc, xt, rows, nbr, S, [&](int row, int col) {
-      const int sidx = row / nbr, rr = row - sidx * nbr;
+      const int sidx = (int)(((float)row + 0.5f) * inv_nbr), rr = row - sidx * nbr;
       return X[(int64_t)(b0 + 1 + sidx) * kTS + rr + col * kNB];
     });
     mfma_block_qr<false>(tc, xt, nbr, Rs, Gs, taus, S);
