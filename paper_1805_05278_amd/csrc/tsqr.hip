@@ -75,19 +75,25 @@ __device__ __forceinline__ double group_sum(double v) {
 }
 
 // Register layout of a block of H rows (H = 64, 128 or 256) in a 512-thread
-// workgroup: RG = H / 8 row groups of 8 consecutive rows; thread t holds rows
-// 8 rg .. 8 rg + 7 (rg = t % RG) of CPT = RG / 8 columns cg CPT .. cg CPT +
-// CPT - 1 (cg = t / RG).  The RG threads of a column group sit in one wave,
-// so column sums are lane reductions.  Each reflector value read from LDS is
-// reused for CPT columns.
+// workgroup: thread t holds 8 rows of CPT = H / 64 columns cg CPT .. cg CPT +
+// CPT - 1 (cg = t / RG, RG = H / 8).  Its rows are four pairs: slot s of lane
+// rg is row 2 rg + 2 RG (s / 2) + s % 2, so that for a fixed slot pair the RG
+// lanes of a column cover 2 RG consecutive rows: global loads and stores
+// coalesce, and the lanes' 16-byte LDS reads of the reflector are
+// consecutive.  The RG threads of a column group sit in one wave, so column
+// sums are lane reductions.  Each reflector value read from LDS is reused for
+// CPT columns.
 template <int H>
 struct Lay {
   static constexpr int RG = H / 8;
   static constexpr int CPT = RG / 8;
+  static __device__ __forceinline__ int row(int rg, int s) {
+    return 2 * rg + 2 * RG * (s >> 1) + (s & 1);
+  }
 };
 
 // One QR step on the rows held in registers (x[u][s]: column cg CPT + u, row
-// 8 rg + s).
+// Lay<H>::row(rg, s)).
 //   first:  plain Householder QR of the rows themselves (pivot row j);
 //   !first: the rows are stacked under the upper triangular R held in Rs.
 // On return x holds the basis (rows below the pivot for `first`, all rows
@@ -102,10 +108,9 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
                                         double (*vbuf)[H], double* taus, double* Wt) {
   constexpr int RG = Lay<H>::RG, CPT = Lay<H>::CPT;
   const int t = threadIdx.x, rg = t % RG, cg = t / RG;
-  // The reflector is posted to vb with rows (8 rg + s, 8 rg + s + 1) as the
-  // pair rg of slice s / 2, so that consecutive lanes read consecutive 16-byte
-  // pairs (a row-major layout would put the lanes 64 bytes apart and on
-  // conflicting banks).
+  // The reflector sits in vb in row order: a lane's pair (s, s + 1) is the
+  // 16-byte word at row(rg, s) = s RG + 2 rg, and consecutive lanes read
+  // consecutive words.
   // Columns are taken CPT at a time so that the owner's register slot U is a
   // compile-time index (a runtime slot would force x out of registers).
   for (int j0 = 0; j0 < nbr; j0 += CPT) {
@@ -118,7 +123,7 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
         double s4[4] = {0.0, 0.0, 0.0, 0.0}, av = 0.0;
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          const int r = 8 * rg + s;
+          const int r = Lay<H>::row(rg, s);
           if (first) {
             s4[s & 3] += (r > j) ? x[U][s] * x[U][s] : 0.0;
             av = (r == j) ? x[U][s] : av;
@@ -138,7 +143,7 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
         double nv[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
-          const int r = 8 * rg + s;
+          const int r = Lay<H>::row(rg, s);
           const double sc = x[U][s] * scale;
           if (first) {
             nv[s] = (r > j) ? sc : ((r == j) ? 1.0 : 0.0);
@@ -344,14 +349,15 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
       const bool first = b == b0;
       const int64_t rstart = ((int64_t)b * a.xrows) / a.nblocks;
       const int rows = (int)((((int64_t)b + 1) * a.xrows) / a.nblocks - rstart);
-      double* src = a.X + rstart + 8 * rg;
+      double* src = a.X + rstart;
       const int64_t ld = a.ldx;
 #pragma unroll
       for (int u = 0; u < CPT; ++u) {
         const int c = cg * CPT + u;
 #pragma unroll
         for (int s = 0; s < 8; ++s)
-          x[u][s] = (c < nbr && 8 * rg + s < rows) ? src[s + (int64_t)c * ld] : 0.0;
+          x[u][s] = (c < nbr && Lay<H>::row(rg, s) < rows)
+                        ? src[Lay<H>::row(rg, s) + (int64_t)c * ld] : 0.0;
       }
       if constexpr (PART != 2) {
         if (first) qr_step<H, true>(x, nbr, Rs, Gs, vbuf, taus, Wt);
@@ -364,7 +370,7 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
         const int c = cg * CPT + u;
 #pragma unroll
         for (int s = 0; s < 8; ++s)
-          if (c < nbr && 8 * rg + s < rows) src[s + (int64_t)c * ld] = x[u][s];
+          if (c < nbr && Lay<H>::row(rg, s) < rows) src[Lay<H>::row(rg, s) + (int64_t)c * ld] = x[u][s];
       }
       build_t(Gs, taus, Wt, nbr);
       double* Tb = a.T + (int64_t)b * kTS;
@@ -376,15 +382,13 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
       } else if (PART != 2) {
         // Z = T V_top^T (upper triangular) in place of T; Rs holds V_top
         // (unit lower top nbr x nbr part of the block's basis) meanwhile.
-        if (rg < kNB / 8) {
 #pragma unroll
-          for (int u = 0; u < CPT; ++u) {
-            const int c = cg * CPT + u;
+        for (int u = 0; u < CPT; ++u) {
+          const int c = cg * CPT + u;
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-              const int r = 8 * rg + s;
-              Rs[r][c] = (r > c) ? x[u][s] : ((r == c) ? 1.0 : 0.0);
-            }
+          for (int s = 0; s < 8; ++s) {
+            const int r = Lay<H>::row(rg, s);
+            if (r < kNB) Rs[r][c] = (r > c) ? x[u][s] : ((r == c) ? 1.0 : 0.0);
           }
         }
         __syncthreads();
@@ -397,15 +401,13 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
         }
         __syncthreads();
         // The block's R (upper triangle of its top rows) seeds the chain.
-        if (rg < kNB / 8) {
 #pragma unroll
-          for (int u = 0; u < CPT; ++u) {
-            const int c = cg * CPT + u;
+        for (int u = 0; u < CPT; ++u) {
+          const int c = cg * CPT + u;
 #pragma unroll
-            for (int s = 0; s < 8; ++s) {
-              const int r = 8 * rg + s;
-              Rs[r][c] = (r <= c && c < nbr) ? x[u][s] : 0.0;
-            }
+          for (int s = 0; s < 8; ++s) {
+            const int r = Lay<H>::row(rg, s);
+            if (r < kNB) Rs[r][c] = (r <= c && c < nbr) ? x[u][s] : 0.0;
           }
         }
       }
@@ -419,7 +421,7 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
       const int c = cg * CPT + u;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        const int r = 8 * rg + s;
+        const int r = Lay<H>::row(rg, s);
         double v = 0.0;
         if (c < nbr && r < rows) {
           const int sidx = r / nbr, rr = r - sidx * nbr;
@@ -435,7 +437,7 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
       const int c = cg * CPT + u;
 #pragma unroll
       for (int s = 0; s < 8; ++s) {
-        const int r = 8 * rg + s;
+        const int r = Lay<H>::row(rg, s);
         if (c < nbr && r < rows) Yn[r + c * kYL] = x[u][s];
       }
     }
