@@ -1259,32 +1259,49 @@ struct DownArgs {
 
 // M = T B into Ms (T upper triangular from global, B in Bs); wave w computes
 // rows [16w, 16w + 16) of M.  MFMA operand roles: A = T tile, B = B tile.
-template <int NQM>
+template <int NQM, int NW>
 __device__ __forceinline__ void down_tb(const double* Tb, double (*Bs)[NQM + 4],
                                         double (*Ms)[NQM + 4], int nbr, int CT) {
-  constexpr int CTM = NQM / 16;
+  // NW waves: wave w computes row tile w % 4 of M and the column tiles of
+  // part w / 4 (with 8 waves the columns are split in two).
+  constexpr int NCP = NW / 4, CTP = NQM / 16 / NCP;
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
-  d4 acc[CTM];
+  const int rt = w & 3, cp = w >> 2;
+  d4 acc[CTP];
 #pragma unroll
-  for (int ct = 0; ct < CTM; ++ct) acc[ct] = d4{0.0, 0.0, 0.0, 0.0};
-  const int i = 16 * w + li;
-  for (int kk = 4 * w; kk < 16; ++kk) {
-    const int k = 4 * kk + lk;
-    const double av = (i < nbr && k < nbr) ? Tb[i + k * kNB] : 0.0;
+  for (int c2 = 0; c2 < CTP; ++c2) acc[c2] = d4{0.0, 0.0, 0.0, 0.0};
+  const int i = 16 * rt + li;
+  // The wave's T values eight at a time (the slot is always in bounds),
+  // masked afterwards: a predicated load per step would wait out a global
+  // latency before each MFMA.
 #pragma unroll
-    for (int ct = 0; ct < CTM; ++ct)
-      if (ct < CT) acc[ct] = mfma64(av, Bs[k][16 * ct + li], acc[ct]);
+  for (int h = 0; h < 2; ++h) {
+    double tv[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) tv[e] = Tb[i + (4 * (8 * h + e) + lk) * kNB];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int k = 4 * (8 * h + e) + lk;
+      const double av = (i < nbr && k < nbr) ? tv[e] : 0.0;
+#pragma unroll
+      for (int c2 = 0; c2 < CTP; ++c2) {
+        const int ct = cp * CTP + c2;
+        if (ct < CT) acc[c2] = mfma64(av, Bs[k][16 * ct + li], acc[c2]);
+      }
+    }
   }
 #pragma unroll
-  for (int ct = 0; ct < CTM; ++ct)
+  for (int c2 = 0; c2 < CTP; ++c2) {
+    const int ct = cp * CTP + c2;
     if (ct < CT)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) Ms[16 * w + lk + 4 * r][16 * ct + li] = acc[ct][r];
+      for (int r = 0; r < 4; ++r) Ms[16 * rt + lk + 4 * r][16 * ct + li] = acc[c2][r];
+  }
 }
 
 // Rows of one leaf block (or one node's stacked children) receive
 // -Y M (+ B on the top rows of a leaf chain's first block).
-template <int RT, int NQM, bool LEAF>
+template <int RT, int NQM, bool LEAF, int NW>
 __device__ __forceinline__ void down_emit(const DownArgs& a, double (*Bs)[NQM + 4],
                                           double (*Ms)[NQM + 4], const double* Yb, int64_t ldy,
                                           int rows, bool first, int64_t rstart, bool top_block,
@@ -1294,7 +1311,7 @@ __device__ __forceinline__ void down_emit(const DownArgs& a, double (*Bs)[NQM + 
   double yf[RT][16];
 #pragma unroll
   for (int s = 0; s < RT; ++s) {
-    const int row = 16 * (w + 4 * s) + li;
+    const int row = 16 * (w + NW * s) + li;
 #pragma unroll
     for (int kk = 0; kk < 16; ++kk) {
       const int k = 4 * kk + lk;
@@ -1318,7 +1335,7 @@ __device__ __forceinline__ void down_emit(const DownArgs& a, double (*Bs)[NQM + 
     }
 #pragma unroll
     for (int s = 0; s < RT; ++s) {
-      const int row = 16 * (w + 4 * s) + li;
+      const int row = 16 * (w + NW * s) + li;
       if (row >= rows) continue;
 #pragma unroll
       for (int g = 0; g < 2; ++g)
@@ -1344,10 +1361,12 @@ __device__ __forceinline__ void down_emit(const DownArgs& a, double (*Bs)[NQM + 
   }
 }
 
-// RT: 16-row tiles per wave (block height 64 RT); NQM: max columns of B;
-// LEAF: emit the panel rows (else the children's B blocks).
-template <int RT, int NQM, bool LEAF>
-__global__ __launch_bounds__(256) void k_chain_down(DownArgs a) {
+// RT: 16-row tiles per wave (block height 16 NW RT); NQM: max columns of B;
+// LEAF: emit the panel rows (else the children's B blocks); NW: waves per
+// workgroup (the leaf launch uses 8, so that each wave holds half as many
+// basis rows and the workgroup has twice the waves to hide its loads).
+template <int RT, int NQM, bool LEAF, int NW>
+__global__ __launch_bounds__(64 * NW) void k_chain_down(DownArgs a) {
   constexpr int BLD = NQM + 4;
   __shared__ __align__(16) double Bs[kNB][BLD];
   __shared__ __align__(16) double Ms[kNB][BLD];
@@ -1358,7 +1377,7 @@ __global__ __launch_bounds__(256) void k_chain_down(DownArgs a) {
   const int nbr = a.nbr, nq = a.nq;
   const int CT = (nq + 15) >> 4;
 
-  for (int i = t; i < kNB * NQM; i += 256) {
+  for (int i = t; i < kNB * NQM; i += 64 * NW) {
     const int r = i % kNB, cc = i / kNB;
     Bs[r][cc] = (r < nbr && cc < nq) ? a.Bin[(int64_t)chain * kBS + r + cc * kNB] : 0.0;
     Ms[r][cc] = 0.0;
@@ -1368,28 +1387,28 @@ __global__ __launch_bounds__(256) void k_chain_down(DownArgs a) {
   if constexpr (LEAF) {
     for (int b = b1 - 1; b >= b0; --b) {
       const bool first = b == b0;
-      down_tb<NQM>(a.T + (int64_t)b * kTS, Bs, Ms, nbr, CT);
+      down_tb<NQM, NW>(a.T + (int64_t)b * kTS, Bs, Ms, nbr, CT);
       __syncthreads();
       if (!first)
-        for (int i = t; i < kNB * NQM; i += 256) {
+        for (int i = t; i < kNB * NQM; i += 64 * NW) {
           const int r = i / NQM, cc = i % NQM;
           Bs[r][cc] -= Ms[r][cc];
         }
       const int64_t rstart = ((int64_t)b * a.xrows) / a.nblocks;
       const int rows = (int)((((int64_t)b + 1) * a.xrows) / a.nblocks - rstart);
-      down_emit<RT, NQM, true>(a, Bs, Ms, a.A + rstart, a.lda, rows, first, rstart, b == 0, b0, CT);
+      down_emit<RT, NQM, true, NW>(a, Bs, Ms, a.A + rstart, a.lda, rows, first, rstart, b == 0, b0, CT);
       __syncthreads();
     }
   } else {
     if (b1 - b0 >= 2) {
-      down_tb<NQM>(a.T + (int64_t)chain * kTS, Bs, Ms, nbr, CT);
+      down_tb<NQM, NW>(a.T + (int64_t)chain * kTS, Bs, Ms, nbr, CT);
       __syncthreads();
-      down_emit<RT, NQM, false>(a, Bs, Ms, a.Y + (int64_t)chain * kYS, kYL, (b1 - b0 - 1) * nbr, false,
+      down_emit<RT, NQM, false, NW>(a, Bs, Ms, a.Y + (int64_t)chain * kYS, kYL, (b1 - b0 - 1) * nbr, false,
                          0, false, b0, CT);
       __syncthreads();
     }
     // First child: B - M (M is zero when the node has a single child).
-    for (int i = t; i < kBS; i += 256) {
+    for (int i = t; i < kBS; i += 64 * NW) {
       const int r = i % kNB, cc = i / kNB;
       a.Bout[(int64_t)b0 * kBS + i] = (r < nbr && cc < nq) ? Bs[r][cc] - Ms[r][cc] : 0.0;
     }
@@ -1537,14 +1556,14 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
     const int stacked = (lv.chain_len - 1) * nbr;  // rows of -Y M per node
     if (stacked <= 64) {
       if (nq > kNB)
-        hipLaunchKernelGGL((k_chain_down<1, 128, false>), dim3(lv.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<1, 128, false, 4>), dim3(lv.nchains), dim3(256), 0, s, d);
       else
-        hipLaunchKernelGGL((k_chain_down<1, 64, false>), dim3(lv.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<1, 64, false, 4>), dim3(lv.nchains), dim3(256), 0, s, d);
     } else {
       if (nq > kNB)
-        hipLaunchKernelGGL((k_chain_down<4, 128, false>), dim3(lv.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<4, 128, false, 4>), dim3(lv.nchains), dim3(256), 0, s, d);
       else
-        hipLaunchKernelGGL((k_chain_down<4, 64, false>), dim3(lv.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<4, 64, false, 4>), dim3(lv.nchains), dim3(256), 0, s, d);
     }
   }
   {
@@ -1568,14 +1587,14 @@ hipError_t tsqr_factor(const TsqrPlan& p, hipStream_t s, double* P, int64_t ldp,
                    2.0 * (double)p.rows * nbr * nq + (double)l0.nblocks * nbr * nbr * nq);
     if (p.leaf_rows == 256) {
       if (nq > kNB)
-        hipLaunchKernelGGL((k_chain_down<4, 128, true>), dim3(l0.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<4, 128, true, 4>), dim3(l0.nchains), dim3(256), 0, s, d);
       else
-        hipLaunchKernelGGL((k_chain_down<4, 64, true>), dim3(l0.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<2, 64, true, 8>), dim3(l0.nchains), dim3(512), 0, s, d);
     } else {
       if (nq > kNB)
-        hipLaunchKernelGGL((k_chain_down<2, 128, true>), dim3(l0.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<2, 128, true, 4>), dim3(l0.nchains), dim3(256), 0, s, d);
       else
-        hipLaunchKernelGGL((k_chain_down<2, 64, true>), dim3(l0.nchains), dim3(256), 0, s, d);
+        hipLaunchKernelGGL((k_chain_down<1, 64, true, 8>), dim3(l0.nchains), dim3(512), 0, s, d);
     }
   }
   return hipGetLastError();

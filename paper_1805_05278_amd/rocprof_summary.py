@@ -37,8 +37,8 @@ _PATTERNS = [
     (r"k_chain_qr<\d+, false, \d+>", "tsqr_chain_qr_tree"),
     (r"k_batched_ls", "batched_ls"),
     (r"k_tsqr_hr\b", "tsqr_hr_root"),
-    (r"k_chain_down<\d+, \d+, false>", "tsqr_down_tree"),
-    (r"k_chain_down<\d+, \d+, true>", "tsqr_down_leaf"),
+    (r"k_chain_down<\d+, \d+, false, \d+>", "tsqr_down_tree"),
+    (r"k_chain_down<\d+, \d+, true, \d+>", "tsqr_down_leaf"),
     (r"k_gemm<\d+, \d+, (true|false), (true|false), 0>", "gemm_f64"),
     (r"k_gemm<\d+, \d+, (true|false), (true|false), 1>", "gemm_f32"),
     (r"k_gemm_bf16<", "gemm_bf16"),
