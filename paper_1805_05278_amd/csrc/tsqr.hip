@@ -572,8 +572,11 @@ __device__ __forceinline__ void load_block(const TileCoord& tc, double (&xt)[8][
     const int col = 16 * ct_ + c;
 #pragma unroll
     for (int s = 0; s < 8; ++s) {
+      // Clamped into the valid corner and masked after the load, so that no
+      // load waits on a predicate and all of them are in flight together.
       const int row = q + 32 * s;
-      v[ct_][s] = (col < nbr && row < nrows) ? at(row, col) : 0.0;
+      const double g = at(min(row, nrows - 1), min(col, nbr - 1));
+      v[ct_][s] = (col < nbr && row < nrows) ? g : 0.0;
     }
   }
 #pragma unroll
@@ -1005,9 +1008,15 @@ struct HRArgs {
 // Stage an nbr x nbr column-major matrix (leading dim kNB) from global
 // memory into LDS (row-major), zero outside nbr.
 __device__ __forceinline__ void hr_stage(double (*S)[kNB + 1], const double* G, int nbr) {
-  for (int i = threadIdx.x; i < kTS; i += 256) {
-    const int r = i % kNB, cc = i / kNB;
-    S[r][cc] = (r < nbr && cc < nbr) ? G[i] : 0.0;
+  // All 16 loads of a thread first (the slot is always in bounds), masked
+  // afterwards, so that they are in flight together.
+  double g[kTS / 256];
+#pragma unroll
+  for (int e = 0; e < kTS / 256; ++e) g[e] = G[threadIdx.x + 256 * e];
+#pragma unroll
+  for (int e = 0; e < kTS / 256; ++e) {
+    const int i = threadIdx.x + 256 * e, r = i % kNB, cc = i / kNB;
+    S[r][cc] = (r < nbr && cc < nbr) ? g[e] : 0.0;
   }
 }
 
@@ -1125,35 +1134,66 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
   }
   __syncthreads();
   // B <- B - T B for the T of every node on the path to leaf block 0 and for
-  // the stacked steps of leaf chain 0.
-  auto path_step = [&](const double* Tg) {
-    hr_stage(Sm, Tg, nbr);
-    __syncthreads();
+  // the stacked steps of leaf chain 0, then M = Z B for leaf block 0.  Step
+  // k's T (path(k)) is loaded into registers while step k - 1's product runs.
+  const int b1c = min(a.chain_len[0], a.nblocks[0]);
+  int nlev = 0;  // path nodes above the leaves
+  for (int lev = a.L; lev >= 1; --lev) nlev += (min(a.chain_len[lev], a.nblocks[lev]) >= 2);
+  const int np = nlev + (b1c - 1) + 1;
+  auto path = [&](int k) -> const double* {
+    if (k < nlev) {
+      int seen = 0;
+      for (int lev = a.L; lev >= 1; --lev)
+        if (min(a.chain_len[lev], a.nblocks[lev]) >= 2 && seen++ == k) return a.T[lev];
+    }
+    if (k < np - 1) return a.T[0] + (int64_t)(b1c - 1 - (k - nlev)) * kTS;
+    return a.T[0];  // leaf block 0: Z
+  };
+  double g[kTS / 256];
+  auto load_t = [&](const double* G) {
+#pragma unroll
+    for (int e = 0; e < kTS / 256; ++e) g[e] = G[t + 256 * e];
+  };
+  auto stage_t = [&]() {
+#pragma unroll
+    for (int e = 0; e < kTS / 256; ++e) {
+      const int i = t + 256 * e, r = i % kNB, cc = i / kNB;
+      Sm[r][cc] = (r < nbr && cc < nbr) ? g[e] : 0.0;
+    }
+  };
+  load_t(path(0));
+  stage_t();
+  __syncthreads();
+  for (int k = 0; k < np; ++k) {
+    if (k + 1 < np) load_t(path(k + 1));
     hr_mm<false>(Mm, Sm, Bm);
     __syncthreads();
+    if (k + 1 == np) break;  // M = Z B of leaf block 0 stays in Mm
+    stage_t();
     for (int i = t; i < kTS; i += 256) {
       const int r = i % kNB, cc = i / kNB;
       Bm[r][cc] -= Mm[r][cc];
     }
     __syncthreads();
-  };
-  for (int lev = a.L; lev >= 1; --lev)
-    if (min(a.chain_len[lev], a.nblocks[lev]) >= 2) path_step(a.T[lev]);
-  {
-    const int b1 = min(a.chain_len[0], a.nblocks[0]);
-    for (int b = b1 - 1; b >= 1; --b) path_step(a.T[0] + (int64_t)b * kTS);
   }
   // Leaf block 0 (local QR with basis V, stored Z = T V_top^T):
   // X = top rows of [B; 0] - V (Z B).
-  hr_stage(Sm, a.T[0], nbr);
-  __syncthreads();
-  hr_mm<false>(Mm, Sm, Bm);
-  __syncthreads();
-  for (int i = t; i < kTS; i += 256) {
-    const int r = i % kNB, cc = i / kNB;
-    double v = 0.0;
-    if (r < nbr && cc < nbr) v = (r > cc) ? a.A0[r + (int64_t)cc * a.lda] : ((r == cc) ? 1.0 : 0.0);
-    Sm[r][cc] = v;
+  {
+    // V_top of leaf block 0, all loads in flight together (indices clamped
+    // into the nbr x nbr corner, masked afterwards).
+    double g[kTS / 256];
+#pragma unroll
+    for (int e = 0; e < kTS / 256; ++e) {
+      const int i = t + 256 * e, r = min(i % kNB, nbr - 1), cc = min(i / kNB, nbr - 1);
+      g[e] = a.A0[r + (int64_t)cc * a.lda];
+    }
+#pragma unroll
+    for (int e = 0; e < kTS / 256; ++e) {
+      const int i = t + 256 * e, r = i % kNB, cc = i / kNB;
+      double v = 0.0;
+      if (r < nbr && cc < nbr) v = (r > cc) ? g[e] : ((r == cc) ? 1.0 : 0.0);
+      Sm[r][cc] = v;
+    }
   }
   __syncthreads();
   hr_mm<false>(Xm, Sm, Mm);
@@ -1229,8 +1269,9 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
   }
   for (int e = t; e < kTS; e += 256) {
     const int r = e % kNB, cc = e / kNB;
+    const double rt = a.Rtop[e];  // the slot is always in bounds
     double lr = 0.0;
-    if (r < nbr && cc < nbr) lr = (r > cc) ? Xm[r][cc] : -Dv[r] * Sv[r] * a.Rtop[r + cc * kNB];
+    if (r < nbr && cc < nbr) lr = (r > cc) ? Xm[r][cc] : -Dv[r] * Sv[r] * rt;
     a.LR[e] = lr;
   }
   for (int e = t; e < kBS; e += 256) {

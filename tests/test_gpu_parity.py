@@ -60,8 +60,11 @@ def check_against_oracle(A, g, tol_r=1e-13, tol_vt=1e-12):
     return f
 
 
+# 20000 x 48, 40000 x 40 and 70000 x 64 take 256-row leaf blocks and the
+# blocked MFMA block QR for first blocks and tree nodes (40 columns: a
+# partial 16-column sub-panel; five children stack 160 rows).
 SHAPES_TSQR = [(1, 1), (5, 3), (64, 64), (100, 7), (130, 64), (1000, 33), (1024, 64),
-               (3001, 64), (20000, 48), (70000, 64)]
+               (3001, 64), (20000, 48), (40000, 40), (70000, 64)]
 
 
 @pytest.mark.parametrize("m,n", SHAPES_TSQR)
@@ -88,7 +91,8 @@ def test_config1_binary_tree_normalised(miqr):
     assert np.linalg.norm(g["Q"].T @ g["Q"] - np.eye(64)) <= 1e-13
 
 
-@pytest.mark.parametrize("m,n", [(200, 65), (300, 100), (1000, 256), (1500, 300), (4096, 513)])
+@pytest.mark.parametrize("m,n", [(200, 65), (300, 100), (1000, 256), (1500, 300), (4096, 513),
+                                 (33000, 100)])
 def test_eg_recursion_matches_oracle(miqr, m, n):
     m_, h = miqr
     A = synth.gaussian(m, n, 200 + n)
