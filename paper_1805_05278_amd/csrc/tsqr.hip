@@ -331,13 +331,25 @@ __device__ __forceinline__ void chain_qr_body(const ChainQRArgs& a) {
   __shared__ double taus[kNB];
   __shared__ double Wt[32 * kNB / 2];
 
-  for (int i = fresh_copy(t); i < kTS; i += 512) {
-    const int r = i % kNB, cc = i / kNB;
-    double v = 0.0;
-    if (!LEAF && r < nbr && cc < nbr) v = a.X[(int64_t)b0 * kTS + i];
-    if (LEAF && PART == 2 && r <= cc && cc < nbr) v = a.R[(int64_t)chain * kTS + i];
-    Rs[r][cc] = v;
-    Gs[r][cc] = 0.0;
+  {
+    // The starting R (tree: child 0's R; stacked leaf blocks: the chain's R
+    // slot), all loads in flight together (slots are always in bounds),
+    // masked afterwards.
+    const int tt = fresh_copy(t);
+    const double* src = !LEAF ? a.X + (int64_t)b0 * kTS
+                              : (PART == 2 ? a.R + (int64_t)chain * kTS : nullptr);
+    double g[kTS / 512];
+#pragma unroll
+    for (int e = 0; e < kTS / 512; ++e) g[e] = src ? src[tt + 512 * e] : 0.0;
+#pragma unroll
+    for (int e = 0; e < kTS / 512; ++e) {
+      const int i = tt + 512 * e, r = i % kNB, cc = i / kNB;
+      double v = 0.0;
+      if (!LEAF && r < nbr && cc < nbr) v = g[e];
+      if (LEAF && PART == 2 && r <= cc && cc < nbr) v = g[e];
+      Rs[r][cc] = v;
+      Gs[r][cc] = 0.0;
+    }
   }
   __syncthreads();
 
@@ -868,13 +880,25 @@ __device__ __forceinline__ void chain_qr_body_mfma(const ChainQRArgs& a) {
   __shared__ MfmaQRShared S;
   double* Wt = &S.Wred[0][0][0];
 
-  for (int i = fresh_copy(t); i < kTS; i += 512) {
-    const int r = i % kNB, cc = i / kNB;
-    double v = 0.0;
-    if (!LEAF && r < nbr && cc < nbr) v = a.X[(int64_t)b0 * kTS + i];
-    if (LEAF && PART == 2 && r <= cc && cc < nbr) v = a.R[(int64_t)chain * kTS + i];
-    Rs[r][cc] = v;
-    Gs[r][cc] = 0.0;
+  {
+    // The starting R (tree: child 0's R; stacked leaf blocks: the chain's R
+    // slot), all loads in flight together (slots are always in bounds),
+    // masked afterwards.
+    const int tt = fresh_copy(t);
+    const double* src = !LEAF ? a.X + (int64_t)b0 * kTS
+                              : (PART == 2 ? a.R + (int64_t)chain * kTS : nullptr);
+    double g[kTS / 512];
+#pragma unroll
+    for (int e = 0; e < kTS / 512; ++e) g[e] = src ? src[tt + 512 * e] : 0.0;
+#pragma unroll
+    for (int e = 0; e < kTS / 512; ++e) {
+      const int i = tt + 512 * e, r = i % kNB, cc = i / kNB;
+      double v = 0.0;
+      if (!LEAF && r < nbr && cc < nbr) v = g[e];
+      if (LEAF && PART == 2 && r <= cc && cc < nbr) v = g[e];
+      Rs[r][cc] = v;
+      Gs[r][cc] = 0.0;
+    }
   }
   if (t < kNB) taus[t] = 0.0;
   __syncthreads();
@@ -1418,10 +1442,20 @@ __global__ __launch_bounds__(64 * NW) void k_chain_down(DownArgs a) {
   const int nbr = a.nbr, nq = a.nq;
   const int CT = (nq + 15) >> 4;
 
-  for (int i = t; i < kNB * NQM; i += 64 * NW) {
-    const int r = i % kNB, cc = i / kNB;
-    Bs[r][cc] = (r < nbr && cc < nq) ? a.Bin[(int64_t)chain * kBS + r + cc * kNB] : 0.0;
-    Ms[r][cc] = 0.0;
+  {
+    // B of this chain / node, all loads in flight together (the slot holds
+    // kNB x 2 kNB, so every index is in bounds), masked afterwards.
+    constexpr int NE = kNB * NQM / (64 * NW);
+    const double* bin = a.Bin + (int64_t)chain * kBS;
+    double g[NE];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) g[e] = bin[t + 64 * NW * e];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) {
+      const int i = t + 64 * NW * e, r = i % kNB, cc = i / kNB;
+      Bs[r][cc] = (r < nbr && cc < nq) ? g[e] : 0.0;
+      Ms[r][cc] = 0.0;
+    }
   }
   __syncthreads();
 
