@@ -707,8 +707,14 @@ __device__ void mfma_block_qr(const TileCoord& tc, double (&xt)[8][4], int nbr,
         if (ss != 0.0) {
           const double nrm = sqrt(alpha * alpha + ss);
           beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
+          // One division for both scalars (two would be serialised on VCC):
+          // with r = 1 / (beta (alpha - beta)), 1 / (alpha - beta) = beta r and
+          // (beta - alpha) / beta = -(alpha - beta)^2 r.  |alpha - beta| is
+          // between nrm and 2 nrm, so the product has the range of alpha^2 + ss.
+          const double amb = alpha - beta;
+          const double r = 1.0 / (beta * amb);
+          scale = beta * r;
+          tau = -(amb * amb) * r;
         }
         double nv[8];
 #pragma unroll
