@@ -26,6 +26,7 @@ import synth
 
 U = 2.0 ** -53
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "householder_3x2.txt")
+GOLDEN_BETA = os.path.join(os.path.dirname(__file__), "golden", "backward_error_3x2.txt")
 
 
 def rel(a, b):
@@ -246,3 +247,56 @@ def test_lstsq_matches_scipy(m, n, nrhs, seed):
     np.testing.assert_allclose(x, xs, rtol=0, atol=1e-12)
     for c in range(nrhs):
         assert oracle.backward_error(A, x[:, c], B[:, c]) <= 1e-15
+
+
+# ------------------------------------------------------ backward error beta
+def read_beta_cases(path):
+    cases = []
+    with open(path) as f:
+        for ln in f:
+            if ln.startswith("case"):
+                _, x0, x1, num2, r2, x2 = ln.split()
+                cases.append((np.array([float(x0), float(x1)]), int(num2), int(r2), int(x2)))
+    return cases
+
+
+def test_backward_error_golden_3x2():
+    """beta(x) = ||A^T r|| / (||A||_F (||A||_F ||x|| + ||r||)) at hand-derived
+    points of the 3 x 2 example (exact integers in the fixture), and zero at
+    the least-squares solution although r != 0."""
+    g = read_golden(GOLDEN)
+    A, b = g["A"], g["b"][:, 0]
+    nA = np.sqrt(66.0)
+    for x, num2, r2, x2 in read_beta_cases(GOLDEN_BETA):
+        want = np.sqrt(num2) / (nA * (nA * np.sqrt(x2) + np.sqrt(r2)))
+        got = oracle.backward_error(A, x, b)
+        assert abs(got - want) <= 8 * U * want, (x, got, want)
+    xls = g["x"][:, 0]
+    assert np.linalg.norm(b - A @ xls) > 1.0
+    assert oracle.backward_error(A, xls, b) <= 1e-16
+
+
+def test_backward_error_properties():
+    """Invariances of the measure (to 1e-8: A^T r cancels to about 1e-6 of
+    ||A|| ||r|| here, so rounding in r shows near 1e-10): unchanged when (A, b)
+    are scaled together,
+    when A's rows and b are permuted alike, and when A's columns are permuted
+    with x; a perturbation dx of the least-squares solution gives beta within
+    [||A^T A dx|| / den, same] computed from its own pieces."""
+    A = synth.gaussian(40, 6, 21)
+    x_true, B = synth.ls_rhs(np.asarray(A), 22, noise=1e-1)
+    b = B[:, 0]
+    x = sla.lstsq(A, b)[0]
+    dx = 1e-6 * synth.rng(23).standard_normal(6)
+    beta = oracle.backward_error(A, x + dx, b)
+    assert beta > 1e-9
+    assert abs(oracle.backward_error(3.0 * A, x + dx, 3.0 * b) - beta) <= 1e-8 * beta
+    p = synth.rng(24).permutation(40)
+    assert abs(oracle.backward_error(A[p], x + dx, b[p]) - beta) <= 1e-8 * beta
+    q = synth.rng(25).permutation(6)
+    assert abs(oracle.backward_error(A[:, q], (x + dx)[q], b) - beta) <= 1e-8 * beta
+    # At x + dx, A^T r = A^T (r_LS - A dx) = -A^T A dx (A^T r_LS = 0).
+    r = b - A @ (x + dx)
+    nA = np.sqrt(np.sum(A * A))
+    want = np.linalg.norm(A.T @ A @ dx) / (nA * (nA * np.linalg.norm(x + dx) + np.linalg.norm(r)))
+    assert abs(beta - want) <= 1e-6 * want

@@ -5,8 +5,11 @@ Each case copies oracle/householder.c, plants one mistake by a textual edit
 off-by-one), compiles the copy on the CPU, routes the oracle module through it
 and checks that at least one pin from test_oracle_pins.py fails.
 """
+import inspect
 import os
 import tempfile
+
+import numpy as np
 
 import pytest
 
@@ -64,3 +67,40 @@ def test_pins_catch_planted_mistake(name):
         finally:
             oracle.use_library(None)
     assert failures > 0, "planted mistake %r passed every pin" % name
+
+
+# Mistakes planted in the backward-error measure (plain numpy in
+# oracle/__init__.py): the function's source is edited, re-executed, and the
+# beta pins must fail.
+BETA_MUTATIONS = {
+    "residual_in_numerator": ("return float(np.linalg.norm(A.T @ r) / den)",
+                              "return float(np.linalg.norm(r) / den)"),
+    "dropped_residual_term": ("den = nA * (nA * np.linalg.norm(x) + np.linalg.norm(r))",
+                              "den = nA * (nA * np.linalg.norm(x))"),
+    "spectral_norm_of_A": ("nA = np.linalg.norm(A)", "nA = np.linalg.norm(A, 2)"),
+    "residual_sign": ("r = b - A @ x", "r = b + A @ x"),
+    "missing_outer_norm": ("den = nA * (nA * np.linalg.norm(x) + np.linalg.norm(r))",
+                           "den = (nA * np.linalg.norm(x) + np.linalg.norm(r))"),
+}
+
+
+def _beta_pin_suite():
+    yield lambda: pins.test_backward_error_golden_3x2()
+    yield lambda: pins.test_backward_error_properties()
+
+
+@pytest.mark.parametrize("name", sorted(BETA_MUTATIONS))
+def test_beta_pins_catch_planted_mistake(name, monkeypatch):
+    old, new = BETA_MUTATIONS[name]
+    src = inspect.getsource(oracle.backward_error)
+    assert src.count(old) == 1, "mutation anchor not found exactly once"
+    ns = {"np": np}
+    exec(src.replace(old, new), ns)
+    monkeypatch.setattr(oracle, "backward_error", ns["backward_error"])
+    failures = 0
+    for check in _beta_pin_suite():
+        try:
+            check()
+        except (AssertionError, ZeroDivisionError, FloatingPointError):
+            failures += 1
+    assert failures > 0, "planted mistake %r passed every beta pin" % name
