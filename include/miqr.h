@@ -62,13 +62,30 @@ typedef enum miqr_precision {
     MIQR_MIXED_BF16 = 2  /* trailing-update GEMMs on BF16 MFMA, FP32 accumulate */
 } miqr_precision;
 
+/* Layout of the kernel T returned by qr_factor. */
+typedef enum miqr_t_layout {
+    /* n x n upper triangular T of Alg. 2's assembly: Q = I - V T V^T. */
+    MIQR_T_FULL = 0,
+    /* The T-avoiding variant of Sec. 8.4: the top level of the recursion is a
+     * right-looking loop over panels of nb columns, each factored by Alg. 2,
+     * and only each panel's own T is formed.  T is nb x n: panel k (columns
+     * k nb .. k nb + w_k - 1, w_k = min(nb, n - k nb)) keeps its w_k x w_k
+     * upper triangular T_k in rows 0 .. w_k - 1 of its columns, zeros below;
+     * Q = Q_0 Q_1 ... Q_{K-1} with Q_k = I - V_k T_k V_k^T (V_k: panel k's
+     * columns of V).  nb = n gives FULL. */
+    MIQR_T_BLOCKED = 1
+} miqr_t_layout;
+
 typedef struct miqr_ctx *miqr_handle;
 
 /* Tuning and output options.  A NULL qr_opts* means all defaults.  Zero in a
- * tuning field means "choose automatically". */
+ * tuning field means "choose automatically": the library's cost model (the
+ * alpha-beta-gamma model of Sec. 3 with launches for messages, fitted on
+ * MI355X) picks the value, per shape; qr_plan reports the choice. */
 typedef struct qr_opts {
-    int64_t b;         /* EG recursion cutoff: columns at or below b go to TSQR
-                          (Alg. 2 base case, n <= b).  Max 64. */
+    int64_t b;         /* Alg. 2 threshold: nodes at most b columns wide are
+                          base cases (1D-CAQR-EG of width <= b, whose own base
+                          case is a TSQR panel of width <= bstar).  0 .. 4096 */
     int64_t leaf_rows; /* TSQR leaf row-block height: 128 or 256 */
     int64_t chain;     /* leaf blocks reduced in sequence by one workgroup */
     int64_t arity;     /* TSQR tree arity above the leaf chains (>= 2) */
@@ -80,6 +97,15 @@ typedef struct qr_opts {
     double *Q;         /* device, optional m x n explicit thin Q (Q D when
                           normalize) */
     int64_t ldq;
+    int64_t bstar;     /* base-case panel width b* (TSQR panels), 1 .. 64,
+                          at most b; 0: automatic (b when b <= 64) */
+    int64_t nb;        /* MIQR_T_BLOCKED: width of the top-level panels,
+                          0 .. 4096 (0: automatic) */
+    int32_t t_layout;  /* miqr_t_layout (0: MIQR_T_FULL) */
+    int32_t no_lookahead; /* MIQR_T_BLOCKED: nonzero keeps every step on the
+                          caller's stream; otherwise panel k + 1 is factored
+                          while an internal stream applies panel k to the
+                          columns beyond it */
 } qr_opts;
 
 /* Host-side result of qr_lstsq. */
@@ -107,8 +133,26 @@ const char *miqr_status_string(miqr_status status);
 const char *miqr_last_error(miqr_handle handle);
 
 /* Bytes of device workspace qr_factor needs for this shape (informational;
- * the handle allocates it on first use). */
+ * the handle allocates it on first use).  0 for invalid sizes or options.
+ * Host only. */
 int64_t qr_workspace_size(int64_t m, int64_t n, const qr_opts *opts);
+
+/* Rows of T that qr_factor writes for this shape and options (the minimum
+ * ldt): n for MIQR_T_FULL, the chosen top-level panel width for
+ * MIQR_T_BLOCKED.  0 for invalid sizes or options.  Host only. */
+int64_t qr_t_rows(int64_t m, int64_t n, const qr_opts *opts);
+
+/* Description of the factorisation plan for this shape and options (lstsq
+ * nonzero: the plan qr_lstsq uses), as JSON text: the tuning (b, bstar, nb,
+ * leaf_rows, chain, arity, t_layout, lookahead; 0 for TSQR parameters chosen
+ * per panel), the cost model's counts and predicted seconds, the workspace
+ * regions in doubles, the recursion nodes [c0, rows, width, n1] (n1 = 0: a
+ * TSQR panel) and the TSQR panels [c0, rows, width, leaf_rows, chain, arity,
+ * levels].  Writes at most len - 1 characters and a NUL to buf (buf may be
+ * NULL) and returns the full length, or -1 for invalid sizes or options.
+ * Host only: needs no device. */
+int64_t qr_plan(int64_t m, int64_t n, const qr_opts *opts, int lstsq, char *buf,
+                int64_t len);
 
 /* Flops (2 per multiply-add) of the GEMMs that the most recent qr_factor on
  * this handle launched: the algorithmic count of the EG updates, reported
@@ -133,11 +177,17 @@ miqr_status miqr_profile_get(miqr_handle handle, int index, char *name,
 /* QR factorisation in place (Alg. 2 with the TSQR base case of Sec. 6.1).
  *   A  (m x n, lda >= m, m >= n >= 1): on return R in the upper triangle and
  *      V's strict lower trapezoid below it.
- *   T  (n x n, ldt >= n): the full upper triangular kernel of Alg. 2's
- *      assembly; its strict lower triangle is set to zero.
+ *   T  MIQR_T_FULL: n x n (ldt >= n), the full upper triangular kernel of
+ *      Alg. 2's assembly, strict lower triangle set to zero.
+ *      MIQR_T_BLOCKED: nb x n (ldt >= qr_t_rows), the panels' kernels (see
+ *      miqr_t_layout).
  *   opts: see qr_opts; opts->Q (if set) receives the explicit thin Q.
- * Errors: MIQR_EINVAL (m < n, n < 1, lda < m, ldt < n, NULL A or T, b out of
- * range, normalize without sign_out, Q with ldq < m), MIQR_ENOMEM, MIQR_EHIP. */
+ * With MIQR_T_BLOCKED and look-ahead the call also enqueues work on the
+ * handle's internal stream, ordered after the caller's stream's earlier work
+ * and joined back into it before the call's last operation.
+ * Errors: MIQR_EINVAL (m < n, n < 1, lda < m, ldt too small, NULL A or T, an
+ * option out of range, normalize without sign_out, Q with ldq < m),
+ * MIQR_ENOMEM, MIQR_EHIP. */
 miqr_status qr_factor(miqr_handle handle, void *stream, int64_t m, int64_t n,
                       double *A, int64_t lda, double *T, int64_t ldt,
                       const qr_opts *opts);
@@ -152,6 +202,15 @@ miqr_status qr_factor(miqr_handle handle, void *stream, int64_t m, int64_t n,
 miqr_status qr_apply_q(miqr_handle handle, void *stream, char trans, int64_t m,
                        int64_t n, int64_t k, const double *VR, int64_t lda,
                        const double *T, int64_t ldt, double *C, int64_t ldc);
+
+/* qr_apply_q for factors in the MIQR_T_BLOCKED layout with panel width nb
+ * (T nb x n, ldt >= min(nb, n)): trans 'N': C <- Q_0 (Q_1 (... Q_{K-1} C)),
+ * 'T': C <- Q_{K-1}^T (... Q_0^T C), each panel as three products.
+ * Errors: as qr_apply_q, and nb < 1. */
+miqr_status qr_apply_q_blocked(miqr_handle handle, void *stream, char trans,
+                               int64_t m, int64_t n, int64_t k, const double *VR,
+                               int64_t lda, const double *T, int64_t ldt,
+                               int64_t nb, double *C, int64_t ldc);
 
 /* Explicit thin Q = (I - V T V^T)[I_n; 0] (m x n, ldq >= m) from the factors.
  * If sign (device, n doubles) is non-NULL the columns are scaled by it
@@ -186,6 +245,20 @@ miqr_status qr_lstsq(miqr_handle handle, void *stream, int64_t m, int64_t n,
 miqr_status qr_solve_r(miqr_handle handle, void *stream, int64_t n,
                        int64_t nrhs, const double *VR, int64_t lda, double *X,
                        int64_t ldx);
+
+/* Backward error of least-squares solutions, the measure every least-squares
+ * result of this library is gated on (the paper defines none):
+ *   beta_j = ||A^T r_j||_2 / (||A||_F (||A||_F ||x_j||_2 + ||r_j||_2)),
+ *   r_j = B[:, j] - A X[:, j],
+ * zero exactly at a least-squares solution, computed in FP64 on the device.
+ *   A (m x n, lda >= m), B (m x nrhs, ldb >= m), X (n x nrhs, ldx >= n):
+ *   device, read only.  beta (host, nrhs doubles) receives the values.
+ * Synchronises the stream.  Uses the handle's workspace.
+ * Errors: MIQR_EINVAL (sizes, NULL pointers), MIQR_ENOMEM, MIQR_EHIP. */
+miqr_status qr_backward_error(miqr_handle handle, void *stream, int64_t m, int64_t n,
+                              int64_t nrhs, const double *A, int64_t lda,
+                              const double *B, int64_t ldb, const double *X,
+                              int64_t ldx, double *beta);
 
 /* One problem of a batched least-squares call (device pointers). */
 typedef struct qr_batch_item {

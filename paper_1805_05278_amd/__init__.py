@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libmiqr.so")
 
 OK, EINVAL, ENOMEM, EHIP, ESINGULAR, ENOCONV, EBUSY, ENOTSUP = range(8)
 FP64, MIXED_FP32, MIXED_BF16 = 0, 1, 2
+T_FULL, T_BLOCKED = 0, 1
 
 _i64 = ctypes.c_int64
 _vp = ctypes.c_void_p
@@ -34,7 +35,8 @@ class MiqrError(RuntimeError):
 class QrOpts(ctypes.Structure):
     _fields_ = [("b", _i64), ("leaf_rows", _i64), ("chain", _i64), ("arity", _i64),
                 ("precision", ctypes.c_int32), ("normalize", ctypes.c_int32),
-                ("sign_out", _vp), ("Q", _vp), ("ldq", _i64)]
+                ("sign_out", _vp), ("Q", _vp), ("ldq", _i64), ("bstar", _i64), ("nb", _i64),
+                ("t_layout", ctypes.c_int32), ("no_lookahead", ctypes.c_int32)]
 
 
 class QrInfo(ctypes.Structure):
@@ -81,6 +83,14 @@ def lib():
         L.miqr_last_error.restype = ctypes.c_char_p
         L.qr_workspace_size.argtypes = [_i64, _i64, ctypes.POINTER(QrOpts)]
         L.qr_workspace_size.restype = _i64
+        L.qr_t_rows.argtypes = [_i64, _i64, ctypes.POINTER(QrOpts)]
+        L.qr_t_rows.restype = _i64
+        L.qr_plan.argtypes = [_i64, _i64, ctypes.POINTER(QrOpts), ctypes.c_int, ctypes.c_char_p,
+                              _i64]
+        L.qr_plan.restype = _i64
+        L.qr_apply_q_blocked.argtypes = [_vp, _vp, ctypes.c_char, _i64, _i64, _i64, _vp, _i64,
+                                         _vp, _i64, _i64, _vp, _i64]
+        L.qr_apply_q_blocked.restype = st
         L.qr_factor.argtypes = [_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64,
                                 ctypes.POINTER(QrOpts)]
         L.qr_factor.restype = st
@@ -94,6 +104,9 @@ def lib():
         L.qr_lstsq.restype = st
         L.qr_solve_r.argtypes = [_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64]
         L.qr_solve_r.restype = st
+        L.qr_backward_error.argtypes = [_vp, _vp, _i64, _i64, _i64, _vp, _i64, _vp, _i64, _vp,
+                                        _i64, ctypes.POINTER(ctypes.c_double)]
+        L.qr_backward_error.restype = st
         L.qr_lstsq_batched.argtypes = [_vp, _vp, _i64, ctypes.POINTER(QrBatchItem),
                                        ctypes.POINTER(QrOpts), ctypes.POINTER(ctypes.c_int32)]
         L.qr_lstsq_batched.restype = st
@@ -223,9 +236,12 @@ class Handle:
 
     @staticmethod
     def opts(b=0, leaf_rows=0, chain=0, arity=0, precision=FP64, normalize=False,
-             sign_out=None, Q=None) -> QrOpts:
+             sign_out=None, Q=None, bstar=0, nb=0, t_layout=T_FULL,
+             lookahead=True) -> QrOpts:
         o = QrOpts()
         o.b, o.leaf_rows, o.chain, o.arity = b, leaf_rows, chain, arity
+        o.bstar, o.nb, o.t_layout = bstar, nb, t_layout
+        o.no_lookahead = 0 if lookahead else 1
         o.precision = precision
         o.normalize = 1 if normalize else 0
         o.sign_out = sign_out.data_ptr() if sign_out is not None else None
@@ -236,6 +252,24 @@ class Handle:
 
     def workspace_size(self, m: int, n: int, opts: Optional[QrOpts] = None) -> int:
         return int(lib().qr_workspace_size(m, n, ctypes.byref(opts) if opts else None))
+
+    @staticmethod
+    def t_rows(m: int, n: int, opts: Optional[QrOpts] = None) -> int:
+        """Rows of T that factor() writes (n, or the BLOCKED panel width)."""
+        return int(lib().qr_t_rows(m, n, ctypes.byref(opts) if opts else None))
+
+    @staticmethod
+    def plan(m: int, n: int, opts: Optional[QrOpts] = None, lstsq: bool = False) -> dict:
+        """The library's plan for this shape (tuning, cost model, workspace
+        regions, recursion nodes and TSQR panels) as a dict."""
+        import json
+        o = ctypes.byref(opts) if opts else None
+        n_chars = lib().qr_plan(m, n, o, 1 if lstsq else 0, None, 0)
+        if n_chars < 0:
+            raise ValueError("invalid shape or options")
+        buf = ctypes.create_string_buffer(n_chars + 1)
+        lib().qr_plan(m, n, o, 1 if lstsq else 0, buf, n_chars + 1)
+        return json.loads(buf.value.decode())
 
     def factor(self, A, T, opts: Optional[QrOpts] = None):
         """In-place QR of A (m x n); T (n x n) receives the kernel."""
@@ -253,6 +287,15 @@ class Handle:
         self._check(lib().qr_apply_q(self._h, _stream(), trans.encode(), m, n, C.shape[1],
                                      vp, lda, tp, ldt, cp, ldc))
 
+    def apply_q_blocked(self, trans: str, VR, T, nb: int, C):
+        """apply_q for factors in the BLOCKED T layout with panel width nb."""
+        vp, lda = _mat(VR, "VR")
+        tp, ldt = _mat(T, "T")
+        cp, ldc = _mat(C, "C")
+        m, n = VR.shape
+        self._check(lib().qr_apply_q_blocked(self._h, _stream(), trans.encode(), m, n,
+                                             C.shape[1], vp, lda, tp, ldt, nb, cp, ldc))
+
     def form_q(self, VR, T, Q, sign=None):
         vp, lda = _mat(VR, "VR")
         tp, ldt = _mat(T, "T")
@@ -266,6 +309,19 @@ class Handle:
         xp, ldx = _mat(X, "X")
         n = VR.shape[1]
         self._check(lib().qr_solve_r(self._h, _stream(), n, X.shape[1], vp, lda, xp, ldx))
+
+    def backward_error(self, A, B, X):
+        """beta_j = ||A^T r_j|| / (||A||_F (||A||_F ||x_j|| + ||r_j||)) per
+        column of X (computed by the library, FP64); returns a list."""
+        ap, lda = _mat(A, "A")
+        bp, ldb = _mat(B, "B")
+        xp, ldx = _mat(X, "X")
+        m, n = A.shape
+        k = B.shape[1]
+        out = (ctypes.c_double * k)()
+        self._check(lib().qr_backward_error(self._h, _stream(), m, n, k, ap, lda, bp, ldb, xp,
+                                            ldx, out))
+        return list(out)
 
     def lstsq(self, A, B, opts: Optional[QrOpts] = None, want_info: bool = True):
         """Least squares in place: A <- factors, B[:n] <- solutions.  Returns

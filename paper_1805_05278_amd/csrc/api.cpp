@@ -11,9 +11,11 @@
 
 #include "batched.h"
 #include "common.h"
+#include "factor.h"
 #include "gemm.h"
 #include "handle.h"
 #include "miqr.h"
+#include "plan.h"
 #include "profiler.h"
 #include "solve.h"
 #include "tsqr.h"
@@ -81,274 +83,126 @@ struct Arena {
   }
 };
 
-struct Tuning {
-  int64_t b = 64;
-  int leaf_rows = 0;
-  int chain = 0;
-  int arity = 0;  // 0: widest node the stacked-R buffer allows (capped at 5)
-};
+bool bad_ptr(const void* p) { return p == nullptr; }
 
-Tuning tuning_from(const qr_opts* o, int64_t m, int64_t n) {
-  Tuning t;
+// Validation of the tuning and output options shared by the entry points
+// (h may be null: the message is then dropped).
+miqr_status check_opts(miqr_handle h, int64_t m, const qr_opts* o) {
+  if (!o) return MIQR_OK;
+  if (o->precision != MIQR_FP64 && o->precision != MIQR_MIXED_FP32 &&
+      o->precision != MIQR_MIXED_BF16)
+    return fail(h, MIQR_EINVAL, "bad precision");
+  if (o->b < 0 || o->b > kMaxB)
+    return fail(h, MIQR_EINVAL, "b must be in [0, " + std::to_string(kMaxB) + "]");
+  if (o->bstar < 0 || o->bstar > kNB) return fail(h, MIQR_EINVAL, "bstar must be in [0, 64]");
+  if (o->b > 0 && o->bstar > o->b) return fail(h, MIQR_EINVAL, "bstar must not exceed b");
+  if (o->nb < 0 || o->nb > kMaxNB)
+    return fail(h, MIQR_EINVAL, "nb must be in [0, " + std::to_string(kMaxNB) + "]");
+  if (o->t_layout != MIQR_T_FULL && o->t_layout != MIQR_T_BLOCKED)
+    return fail(h, MIQR_EINVAL, "bad t_layout");
+  if (o->leaf_rows != 0 && o->leaf_rows != 128 && o->leaf_rows != 256)
+    return fail(h, MIQR_EINVAL, "leaf_rows must be 0, 128 or 256");
+  if (o->chain < 0 || o->arity < 0 || o->arity == 1)
+    return fail(h, MIQR_EINVAL, "chain must be >= 0 and arity 0 or >= 2");
+  if (o->normalize && !o->sign_out) return fail(h, MIQR_EINVAL, "normalize needs sign_out");
+  if (o->Q && o->ldq < m) return fail(h, MIQR_EINVAL, "ldq < m");
+  return MIQR_OK;
+}
+
+// The look-ahead stream and events of the handle (created on first use, at
+// the default priority).
+miqr_status ensure_lookahead(miqr_handle h, Lookahead* la) {
+  hipError_t e = hipSuccess;
+  if (!h->aux) e = hipStreamCreateWithFlags(&h->aux, hipStreamNonBlocking);
+  if (e == hipSuccess && !h->ev_panel)
+    e = hipEventCreateWithFlags(&h->ev_panel, hipEventDisableTiming);
+  if (e == hipSuccess && !h->ev_update)
+    e = hipEventCreateWithFlags(&h->ev_update, hipEventDisableTiming);
+  if (e != hipSuccess) return hip_fail(h, e, "look-ahead stream");
+  la->aux = h->aux;
+  la->ev_panel = h->ev_panel;
+  la->ev_update = h->ev_update;
+  return MIQR_OK;
+}
+
+// Tuning for a call, through the handle's cache (the cost model's choice
+// depends only on the shape and the fields the caller fixed).
+Tuning tuning_for(miqr_handle h, int64_t m, int64_t n, const qr_opts* o, bool lstsq) {
+  TuneKey k{m, n, lstsq ? 1 : 0, 0, 0, 0, 0, 0, 0, 0, 0};
   if (o) {
-    if (o->b > 0) t.b = o->b;
-    if (o->leaf_rows > 0) t.leaf_rows = (int)o->leaf_rows;
-    if (o->chain > 0) t.chain = (int)o->chain;
-    if (o->arity >= 2) t.arity = (int)o->arity;
+    k.b = o->b;
+    k.bstar = o->bstar;
+    k.nb = o->nb;
+    k.leaf_rows = o->leaf_rows;
+    k.chain = o->chain;
+    k.arity = o->arity;
+    k.layout = o->t_layout;
+    k.nola = o->no_lookahead;
   }
-  t.b = std::min<int64_t>(t.b, std::min<int64_t>(n, kNB));
-  (void)m;
+  if (h) {
+    auto it = h->tune_cache.find(k);
+    if (it != h->tune_cache.end()) return it->second;
+  }
+  const Tuning t = choose_tuning(m, n, o, lstsq);
+  if (h) {
+    if (h->tune_cache.size() > 4096) h->tune_cache.clear();
+    h->tune_cache[k] = t;
+  }
   return t;
 }
 
-int64_t split_point(int64_t nk, int64_t b) {
-  // Alg. 2 splits at floor(n/2); any split gives the same factors in exact
-  // arithmetic.  Rounding the left width up to a multiple of the cutoff keeps
-  // every panel full width and the GEMM operands aligned.
-  int64_t n1 = ((nk / 2 + b - 1) / b) * b;
-  if (n1 >= nk) n1 = nk / 2;
-  return std::max<int64_t>(n1, 1);
+// Rows of T a factorisation writes: n (FULL) or the top-level panel width.
+int64_t t_rows(const Tuning& t, int64_t n) {
+  return t.t_layout == T_BLOCKED ? std::min<int64_t>(std::max<int64_t>(t.nb, 1), n) : n;
 }
 
-// Largest TSQR workspace over the panels the recursion will visit.
-void max_panel_ws(int64_t mk, int64_t nk, const Tuning& t, int64_t* best) {
-  if (nk <= t.b) {
-    TsqrPlan p = tsqr_plan(mk, (int)nk, t.leaf_rows, t.chain, t.arity, nullptr);
-    *best = std::max(*best, p.workspace_doubles);
-    return;
+// Factor with the given tuning, the workspace regions carved from `base`
+// (FactorLayout order).
+miqr_status factor_with(miqr_handle h, hipStream_t s, const Tuning& tune, const FactorWs& w,
+                        const FactorArgs& a) {
+  Lookahead la;
+  if (tune.t_layout == T_BLOCKED && tune.lookahead) {
+    miqr_status st = ensure_lookahead(h, &la);
+    if (st != MIQR_OK) return st;
   }
-  const int64_t n1 = split_point(nk, t.b);
-  max_panel_ws(mk, n1, t, best);
-  max_panel_ws(mk - n1, nk - n1, t, best);
-}
-
-struct FactorLayout {
-  int64_t tsqr = 0, wa = 0, wb = 0, scratch = 0, total = 0;
-};
-
-FactorLayout factor_layout(int64_t m, int64_t n, const Tuning& t) {
-  FactorLayout L;
-  max_panel_ws(m, n, t, &L.tsqr);
-  const int64_t n1 = (n > t.b) ? split_point(n, t.b) : 0;
-  const int64_t n2 = n - n1;
-  L.wa = std::max<int64_t>(n1 * n2, 1);
-  L.wb = L.wa;
-  // Split-K partials: room for 512 splits of a 128 x 128 product.
-  L.scratch = std::max<int64_t>(int64_t(8) << 20, 4 * L.wa);
-  L.total = L.tsqr + L.wa + L.wb + L.scratch + 4 * 32;
-  return L;
-}
-
-struct EgCtx {
-  hipStream_t s;
-  double* A;
-  int64_t lda;
-  double* T;
-  int64_t ldt;
-  Tuning tune;
-  double* tsqr_ws;
-  double* Wa;
-  double* Wb;
-  double* scratch;
-  int64_t scratch_n;
-  int update_compute;
   double flops = 0.0;
-  hipError_t err = hipSuccess;
-  // thin Q for a single-panel factorisation
-  double* Q = nullptr;
-  int64_t ldq = 0;
-  int normalize = 0;
-  double* sign = nullptr;
-  // Least-squares use: leave the T12 blocks of the nodes on the recursion's
-  // right spine (root, root.right, ...) unassembled.  No trailing update
-  // needs them (a node's T is used only when it is a left half); Q^T b is
-  // then applied along the spine (apply_qt_spine).
-  bool skip_spine_t = false;
-};
-
-void run_gemm(EgCtx& e, const GemmDesc& d) {
-  if (e.err != hipSuccess) return;
-  e.err = gemm(d, e.s, e.scratch, e.scratch_n, &e.flops);
+  hipError_t e = run_factor(s, la, tune, w, a, &flops);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_factor");
+  h->gemm_flops = flops;
+  return MIQR_OK;
 }
 
-// Alg. 2 (QR-EG) on the sub-problem with top-left corner (r0, c0), mk rows
-// (to the bottom of A) and nk columns.
-void eg(EgCtx& e, int64_t r0, int64_t c0, int64_t mk, int64_t nk, bool spine = true) {
-  if (e.err != hipSuccess) return;
-  double* A = e.A;
-  const int64_t lda = e.lda, ldt = e.ldt;
-  if (nk <= e.tune.b) {
-    TsqrPlan p = tsqr_plan(mk, (int)nk, e.tune.leaf_rows, e.tune.chain, e.tune.arity, e.tsqr_ws);
-    e.err = tsqr_factor(p, e.s, A + r0 + c0 * lda, lda, e.T + c0 + c0 * ldt, ldt, e.Q, e.ldq,
-                        e.normalize, e.sign);
-    return;
-  }
-  const int64_t n1 = split_point(nk, e.tune.b), n2 = nk - n1;
-  eg(e, r0, c0, mk, n1, false);
-  double* VL = A + r0 + c0 * lda;
-  double* C = A + r0 + (c0 + n1) * lda;
-  double* TL = e.T + c0 + c0 * ldt;
-  GemmDesc d;
-  // M1 = V_L^T C
-  d = GemmDesc();
-  d.ta = 'T'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = mk;
-  d.A = VL; d.lda = lda; d.maskA = MASK_UNIT_LOWER;
-  d.B = C; d.ldb = lda; d.C = e.Wa; d.ldc = n1; d.compute = e.update_compute;
-  run_gemm(e, d);
-  // M2 = T_L^T M1
-  d = GemmDesc();
-  d.ta = 'T'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = n1;
-  d.A = TL; d.lda = ldt; d.maskA = MASK_UPPER;
-  d.B = e.Wa; d.ldb = n1; d.C = e.Wb; d.ldc = n1;
-  run_gemm(e, d);
-  // [B12; B22] = C - V_L M2
-  d = GemmDesc();
-  d.ta = 'N'; d.tb = 'N'; d.M = mk; d.N = n2; d.K = n1; d.alpha = -1.0; d.beta = 1.0;
-  d.A = VL; d.lda = lda; d.maskA = MASK_UNIT_LOWER;
-  d.B = e.Wb; d.ldb = n1; d.C = C; d.ldc = lda; d.compute = e.update_compute;
-  run_gemm(e, d);
-  eg(e, r0 + n1, c0 + n1, mk - n1, n2, spine);
-  if (spine && e.skip_spine_t) return;
-  double* VR = A + (r0 + n1) + (c0 + n1) * lda;
-  double* TR = e.T + (c0 + n1) + (c0 + n1) * ldt;
-  // M3 = V_L^T [0; V_R] = V_L[n1:, :]^T V_R
-  d = GemmDesc();
-  d.ta = 'T'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = mk - n1;
-  d.A = A + (r0 + n1) + c0 * lda; d.lda = lda;
-  d.B = VR; d.ldb = lda; d.maskB = MASK_UNIT_LOWER; d.C = e.Wa; d.ldc = n1;
-  run_gemm(e, d);
-  // M4 = M3 T_R
-  d = GemmDesc();
-  d.ta = 'N'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = n2;
-  d.A = e.Wa; d.lda = n1; d.B = TR; d.ldb = ldt; d.maskB = MASK_UPPER;
-  d.C = e.Wb; d.ldc = n1;
-  run_gemm(e, d);
-  // T12 = -T_L M4
-  d = GemmDesc();
-  d.ta = 'N'; d.tb = 'N'; d.M = n1; d.N = n2; d.K = n1; d.alpha = -1.0;
-  d.A = TL; d.lda = ldt; d.maskA = MASK_UPPER; d.B = e.Wb; d.ldb = n1;
-  d.C = e.T + c0 + (c0 + n1) * ldt; d.ldc = ldt;
-  run_gemm(e, d);
-}
-
-bool bad_ptr(const void* p) { return p == nullptr; }
-
-miqr_status do_factor(miqr_handle h, hipStream_t s, int64_t m, int64_t n, double* A, int64_t lda,
-                      double* T, int64_t ldt, const qr_opts* o, int update_compute,
-                      bool skip_spine_t = false) {
-  const Tuning tune = tuning_from(o, m, n);
-  FactorLayout L = factor_layout(m, n, tune);
+// Factor in the handle's workspace (grown to the layout first).
+miqr_status do_factor(miqr_handle h, hipStream_t s, const Tuning& tune, const FactorArgs& a) {
+  const FactorLayout L = factor_layout(a.m, a.n, tune, a.Q != nullptr);
   miqr_status st = ensure_ws(h, (size_t)L.total * sizeof(double));
   if (st != MIQR_OK) return st;
-  Arena ar{(double*)h->ws};
-  EgCtx e;
-  e.s = s;
-  e.A = A;
-  e.lda = lda;
-  e.T = T;
-  e.ldt = ldt;
-  e.tune = tune;
-  e.tsqr_ws = ar.take(L.tsqr);
-  e.Wa = ar.take(L.wa);
-  e.Wb = ar.take(L.wb);
-  e.scratch = ar.take(L.scratch);
-  e.scratch_n = L.scratch;
-  e.update_compute = update_compute;
-  e.skip_spine_t = skip_spine_t;
-  // A single TSQR panel can emit Q and the normalised R itself, except for
-  // square matrices whose last reflector is switched afterwards.
-  const bool single = n <= tune.b && m > n;
-  const int normalize = o ? o->normalize : 0;
-  double* sign = o ? o->sign_out : nullptr;
-  double* Q = o ? o->Q : nullptr;
-  const int64_t ldq = o ? o->ldq : 0;
-  zero_strict_lower(s, n, T, ldt);
-  if (single) {
-    e.Q = Q;
-    e.ldq = ldq;
-    e.normalize = normalize;
-    e.sign = sign;
-  }
-  eg(e, 0, 0, m, n);
-  if (e.err != hipSuccess) return hip_fail(h, e.err, "qr_factor");
-  if (m == n) square_last_column(s, n, A, lda, T, ldt);
-  if (!single) {
-    if (normalize) normalize_r(s, n, A, lda, sign);
-    if (Q) {
-      miqr_status st2 = qr_form_q(h, s, m, n, A, lda, T, ldt, normalize ? sign : nullptr, Q, ldq);
-      if (st2 != MIQR_OK) return st2;
-    }
-  }
-  h->gemm_flops = e.flops;
-  hipError_t le = hipGetLastError();
-  if (le != hipSuccess) return hip_fail(h, le, "qr_factor launch");
-  return MIQR_OK;
+  const FactorWs w = carve_factor((double*)h->ws, L);
+  return factor_with(h, s, tune, w, a);
 }
 
-// C <- Q C or Q^T C with Q = I - V T V^T (three products, right to left).
-miqr_status do_apply(miqr_handle h, hipStream_t s, char trans, int64_t m, int64_t n, int64_t k,
-                     const double* VR, int64_t lda, const double* T, int64_t ldt, double* C,
-                     int64_t ldc, double* W1, double* W2, double* scratch, int64_t scratch_n) {
-  if (k == 0) return MIQR_OK;
-  GemmDesc d;
-  d.ta = 'T'; d.tb = 'N'; d.M = n; d.N = k; d.K = m;
-  d.A = VR; d.lda = lda; d.maskA = MASK_UNIT_LOWER; d.B = C; d.ldb = ldc; d.C = W1; d.ldc = n;
-  hipError_t e = gemm(d, s, scratch, scratch_n);
-  if (e == hipSuccess) {
-    d = GemmDesc();
-    d.ta = (trans == 'T') ? 'T' : 'N'; d.tb = 'N'; d.M = n; d.N = k; d.K = n;
-    d.A = T; d.lda = ldt; d.maskA = MASK_UPPER; d.B = W1; d.ldb = n; d.C = W2; d.ldc = n;
-    e = gemm(d, s, scratch, scratch_n);
-  }
-  if (e == hipSuccess) {
-    d = GemmDesc();
-    d.ta = 'N'; d.tb = 'N'; d.M = m; d.N = k; d.K = n; d.alpha = -1.0; d.beta = 1.0;
-    d.A = VR; d.lda = lda; d.maskA = MASK_UNIT_LOWER; d.B = W2; d.ldb = n; d.C = C; d.ldc = ldc;
-    e = gemm(d, s, scratch, scratch_n);
-  }
-  if (e != hipSuccess) return hip_fail(h, e, "apply_q");
-  return MIQR_OK;
-}
-
-// C <- Q^T C for factors whose right-spine T12 blocks were not assembled:
-// Q = Q_L Q_R at every spine node, so Q^T C applies (V_L, T_L)^T to the
-// node's rows and moves on to the right child, down to the last panel.
-miqr_status apply_qt_spine(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64_t k,
-                           const double* VR, int64_t lda, const double* T, int64_t ldt,
-                           double* C, int64_t ldc, int64_t b, double* W1, double* W2,
-                           double* scratch, int64_t scratch_n) {
-  int64_t r0 = 0, c0 = 0, mk = m, nk = n;
-  for (;;) {
-    const int64_t w = nk <= b ? nk : split_point(nk, b);
-    miqr_status st = do_apply(h, s, 'T', mk, w, k, VR + r0 + c0 * lda, lda, T + c0 + c0 * ldt,
-                              ldt, C + r0, ldc, W1, W2, scratch, scratch_n);
-    if (st != MIQR_OK || w == nk) return st;
-    r0 += w;
-    c0 += w;
-    mk -= w;
-    nk -= w;
-  }
-}
-
-// beta(x) = max_c ||A^T r_c|| / (||A||_F (||A||_F ||x_c|| + ||r_c||)),
-// r = b - A x, all FP64 on the device (A0, B0 originals; X solutions).
-// R (m x k) and U (n x k) are scratch.  Synchronises the stream.
+// beta(x)_c = ||A^T r_c|| / (||A||_F (||A||_F ||x_c|| + ||r_c||)),
+// r = b - A x, all FP64 on the device (A0, B0 originals; X solutions).  Rr
+// (m x k) and U (n x k) are scratch, nrm 3k + n doubles.  Writes every
+// right-hand side's value to out (host, k doubles) when given and returns the
+// largest.  Synchronises the stream.
 double backward_error_dev(hipStream_t s, int64_t m, int64_t n, int64_t k, const double* A0,
-                          const double* B0, const double* X, int64_t ldx, double* Rr, double* U,
-                          double* nrm, double* sc, int64_t scn, hipError_t* err) {
-  copy_matrix(s, m, k, B0, m, Rr, m);
+                          int64_t lda, const double* B0, int64_t ldb, const double* X,
+                          int64_t ldx, double* Rr, double* U, double* nrm, double* sc, int64_t scn,
+                          hipError_t* err, double* out = nullptr) {
+  copy_matrix(s, m, k, B0, ldb, Rr, m);
   GemmDesc d;
   d.ta = 'N'; d.tb = 'N'; d.M = m; d.N = k; d.K = n; d.alpha = -1.0; d.beta = 1.0;
-  d.A = A0; d.lda = m; d.B = X; d.ldb = ldx; d.C = Rr; d.ldc = m;
+  d.A = A0; d.lda = lda; d.B = X; d.ldb = ldx; d.C = Rr; d.ldc = m;
   hipError_t e = gemm(d, s, sc, scn);
   d = GemmDesc();
   d.ta = 'T'; d.tb = 'N'; d.M = n; d.N = k; d.K = m;
-  d.A = A0; d.lda = m; d.B = Rr; d.ldb = m; d.C = U; d.ldc = n;
+  d.A = A0; d.lda = lda; d.B = Rr; d.ldb = m; d.C = U; d.ldc = n;
   if (e == hipSuccess) e = gemm(d, s, sc, scn);
   column_sumsq(s, m, k, Rr, m, nrm);
   column_sumsq(s, n, k, U, n, nrm + k);
   column_sumsq(s, n, k, X, ldx, nrm + 2 * k);
-  column_sumsq(s, m, n, A0, m, nrm + 3 * k);
+  column_sumsq(s, m, n, A0, lda, nrm + 3 * k);
   std::vector<double> hn(3 * k + n);
   if (e == hipSuccess)
     e = hipMemcpyAsync(hn.data(), nrm, sizeof(double) * hn.size(), hipMemcpyDeviceToHost, s);
@@ -362,9 +216,55 @@ double backward_error_dev(hipStream_t s, int64_t m, int64_t n, int64_t k, const 
   for (int64_t c = 0; c < k; ++c) {
     const double rn = std::sqrt(hn[c]), gn = std::sqrt(hn[k + c]), xn = std::sqrt(hn[2 * k + c]);
     const double den = fa * (fa * xn + rn);
-    worst = std::max(worst, den > 0 ? gn / den : 0.0);
+    const double be = den > 0 ? gn / den : 0.0;
+    if (out) out[c] = be;
+    worst = std::max(worst, be);
   }
   return worst;
+}
+
+// Q^T B with the factors in the tuning's T layout (FULL factors from least
+// squares have their right-spine T12 blocks unassembled).  W1, W2: n x k.
+hipError_t apply_qt(hipStream_t s, const Tuning& t, int64_t m, int64_t n, int64_t k,
+                    const double* A, int64_t lda, const double* T, int64_t ldt, double* B,
+                    int64_t ldb, double* W1, double* W2, double* sc, int64_t scn) {
+  if (t.t_layout == T_BLOCKED)
+    return apply_q_blocked(s, 'T', m, n, k, A, lda, T, ldt, t.nb, B, ldb, W1, W2, sc, scn);
+  return apply_qt_spine(s, m, n, k, A, lda, T, ldt, B, ldb, t, W1, W2, sc, scn);
+}
+
+// FP64 least squares on carved regions: factor, B <- Q^T B, singularity
+// check, back substitution R x = (Q^T b)[0:n].
+miqr_status lstsq_core(miqr_handle h, hipStream_t s, const Tuning& tune, const FactorWs& f,
+                       int64_t m, int64_t n, int64_t k, double* A, int64_t lda, double* B,
+                       int64_t ldb, double* T, double* W1, double* W2, qr_info* info) {
+  FactorArgs a;
+  a.m = m;
+  a.n = n;
+  a.A = A;
+  a.lda = lda;
+  a.T = T;
+  a.ldt = t_rows(tune, n);
+  a.update_compute = COMPUTE_F64;
+  a.skip_spine_t = true;
+  miqr_status st = factor_with(h, s, tune, f, a);
+  if (st != MIQR_OK) return st;
+  hipError_t e = apply_qt(s, tune, m, n, k, A, lda, T, a.ldt, B, ldb, W1, W2, f.scratch,
+                          f.scratch_n);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq apply");
+  find_zero_diagonal(s, n, A, lda, h->dflag);
+  int flag = 0;
+  e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq");
+  if (flag) {
+    if (info) info->singular_index = flag;
+    return fail(h, MIQR_ESINGULAR, "R(" + std::to_string(flag - 1) + ") == 0");
+  }
+  e = solve_upper(s, n, k, A, lda, B, ldb, f.scratch, f.scratch_n);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq solve");
+  if (info) info->precision_used = MIQR_FP64;
+  return MIQR_OK;
 }
 
 // Least squares with the mixed form: the factorisation runs with FP32/BF16
@@ -377,25 +277,24 @@ double backward_error_dev(hipStream_t s, int64_t m, int64_t n, int64_t k, const 
 // fails over to the FP64 path if the gate is not met within maxit steps, or
 // as soon as the observed contraction rate shows it will not be.
 struct MixedWs {
-  double *T, *A0, *B0, *Rinv, *X, *Rr, *S, *P, *Tv, *Qv, *U, *W1, *W2, *sc, *nrm, *coef;
-  int64_t scn;
+  double *T, *A0, *B0, *Rinv, *X, *Rr, *S, *P, *Tv, *Qv, *U, *W1, *W2, *nrm, *coef;
 };
-
-miqr_status lstsq_fp64(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64_t k, double* A,
-                       int64_t lda, double* B, int64_t ldb, const qr_opts* o, double* T,
-                       double* W1, double* W2, double* sc, int64_t scn, qr_info* info);
 
 miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64_t k, double* A,
                         int64_t lda, double* B, int64_t ldb, const qr_opts* o, int comp,
                         qr_info* info) {
-  const Tuning tune = tuning_from(o, m, n);
-  FactorLayout L = factor_layout(m, n, tune);
+  const Tuning tune = tuning_for(h, m, n, o, true);
+  const FactorLayout L = factor_layout(m, n, tune);
+  const int64_t tr = t_rows(tune, n);
   MixedWs w;
+  FactorWs f;
   // The workspace size is taken from the same carving that assigns the
   // pointers (a dry run over a null base), so the two cannot disagree.
-  auto carve = [&](Arena& ar) {
-    ar.take(L.total);
-    w.T = ar.take(n * n);
+  auto carve = [&](double* base) {
+    f = carve_factor(base, L);
+    Arena ar{base};
+    ar.off = f.doubles;
+    w.T = ar.take(tr * n);
     w.Rinv = ar.take(n * n);
     w.A0 = ar.take(m * n);
     w.B0 = ar.take(m * k);
@@ -410,31 +309,31 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
     w.W2 = ar.take(n * k);
     w.nrm = ar.take(4 * k + n + 8);
     w.coef = ar.take(2 * k + 8);
+    return ar.off;
   };
-  Arena dry{nullptr};
-  carve(dry);
-  miqr_status st = ensure_ws(h, (size_t)dry.off * sizeof(double));
+  const int64_t need = carve(nullptr);
+  miqr_status st = ensure_ws(h, (size_t)need * sizeof(double));
   if (st != MIQR_OK) return st;
-  Arena ar{(double*)h->ws};
-  carve(ar);
-  {
-    Arena far{(double*)h->ws};
-    far.take(L.tsqr);
-    far.take(L.wa);
-    far.take(L.wb);
-    w.sc = far.take(L.scratch);
-    w.scn = L.scratch;
-  }
+  carve((double*)h->ws);
   const double tol = 1e-13, floor = 4.0 * 0x1p-53;
   const int maxit = 100;
   copy_matrix(s, m, n, A, lda, w.A0, m);
   copy_matrix(s, m, k, B, ldb, w.B0, m);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed copies");
-  st = do_factor(h, s, m, n, A, lda, w.T, n, o, comp, true);
-  if (st != MIQR_OK) return st;
-  e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed factor");
+  {
+    FactorArgs a;
+    a.m = m;
+    a.n = n;
+    a.A = A;
+    a.lda = lda;
+    a.T = w.T;
+    a.ldt = tr;
+    a.update_compute = comp;
+    a.skip_spine_t = true;
+    st = factor_with(h, s, tune, f, a);
+    if (st != MIQR_OK) return st;
+  }
   find_zero_diagonal(s, n, A, lda, h->dflag);
   int flag = 0;
   e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
@@ -450,7 +349,7 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
     GemmDesc d;
     d.ta = ta; d.tb = 'N'; d.M = M; d.N = N; d.K = K; d.alpha = alpha; d.beta = beta;
     d.A = Ap; d.lda = la; d.maskA = ma; d.B = Bp; d.ldb = lb; d.C = Cp; d.ldc = lc;
-    e = gemm(d, s, w.sc, w.scn);
+    e = gemm(d, s, f.scratch, f.scratch_n);
   };
   std::vector<double> hn(4 * k + n + 8), hc(2 * k + 8);
   auto fetch_norms = [&](int cnt) {
@@ -461,14 +360,12 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
   if (!flag) {
     // R^{-1} (upper): solve R Z = I.
     set_identity(s, n, n, w.Rinv, n);
-    e = solve_upper(s, n, n, A, lda, w.Rinv, n, w.sc, w.scn);
+    e = solve_upper(s, n, n, A, lda, w.Rinv, n, f.scratch, f.scratch_n);
     // x0 = R^{-1} (Q^T b)[0:n]
     copy_matrix(s, m, k, w.B0, m, w.Rr, m);
-    if (e == hipSuccess) {
-      miqr_status s2 = apply_qt_spine(h, s, m, n, k, A, lda, w.T, n, w.Rr, m, tune.b, w.W1, w.W2,
-                                      w.sc, w.scn);
-      if (s2 != MIQR_OK) return s2;
-    }
+    if (e == hipSuccess)
+      e = apply_qt(s, tune, m, n, k, A, lda, w.T, tr, w.Rr, m, w.W1, w.W2, f.scratch,
+                   f.scratch_n);
     G('N', n, k, n, 1.0, w.Rinv, n, MASK_UPPER, w.Rr, m, 0.0, w.X, n);
     // ||A||_F
     column_sumsq(s, m, n, w.A0, m, w.nrm + 4 * k);
@@ -564,43 +461,18 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
   // Fallback: refactor the original in FP64.
   copy_matrix(s, m, n, w.A0, m, A, lda);
   copy_matrix(s, m, k, w.B0, m, B, ldb);
-  qr_opts o64 = o ? *o : qr_opts{};
-  o64.precision = MIQR_FP64;
-  st = lstsq_fp64(h, s, m, n, k, A, lda, B, ldb, &o64, w.T, w.W1, w.W2, w.sc, w.scn, info);
+  st = lstsq_core(h, s, tune, f, m, n, k, A, lda, B, ldb, w.T, w.W1, w.W2, info);
   if (info) {
     info->iterations = iters;
     info->fallback = 1;
   }
   if (st != MIQR_OK) return st;
   if (info) {
-    info->backward_error = backward_error_dev(s, m, n, k, w.A0, w.B0, B, ldb, w.Rr, w.U, w.nrm,
-                                              w.sc, w.scn, &e);
+    info->backward_error = backward_error_dev(s, m, n, k, w.A0, m, w.B0, m, B, ldb, w.Rr, w.U,
+                                              w.nrm, f.scratch, f.scratch_n, &e);
     if (e != hipSuccess) return hip_fail(h, e, "lstsq_mixed fallback");
   }
   return fail(h, MIQR_ENOCONV, "refinement did not reach 1e-13; FP64 result returned");
-}
-
-// FP64 least squares on the factors: factor, c = Q^T b, back substitution.
-miqr_status lstsq_fp64(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int64_t k, double* A,
-                       int64_t lda, double* B, int64_t ldb, const qr_opts* o, double* T,
-                       double* W1, double* W2, double* sc, int64_t scn, qr_info* info) {
-  miqr_status st = do_factor(h, s, m, n, A, lda, T, n, o, COMPUTE_F64, true);
-  if (st != MIQR_OK) return st;
-  st = apply_qt_spine(h, s, m, n, k, A, lda, T, n, B, ldb, tuning_from(o, m, n).b, W1, W2, sc, scn);
-  if (st != MIQR_OK) return st;
-  find_zero_diagonal(s, n, A, lda, h->dflag);
-  int flag = 0;
-  hipError_t e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq");
-  if (flag) {
-    if (info) info->singular_index = flag;
-    return fail(h, MIQR_ESINGULAR, "R(" + std::to_string(flag - 1) + ") == 0");
-  }
-  e = solve_upper(s, n, k, A, lda, B, ldb, sc, scn);
-  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq solve");
-  if (info) info->precision_used = MIQR_FP64;
-  return MIQR_OK;
 }
 
 // Pinned host staging for `count` tasks and statuses.  Waits for the previous
@@ -672,6 +544,9 @@ miqr_status miqr_destroy(miqr_handle h) {
   if (h->pin_tasks) hipHostFree(h->pin_tasks);
   if (h->pin_status) hipHostFree(h->pin_status);
   if (h->table_ev) hipEventDestroy(h->table_ev);
+  if (h->ev_panel) hipEventDestroy(h->ev_panel);
+  if (h->ev_update) hipEventDestroy(h->ev_update);
+  if (h->aux) hipStreamDestroy(h->aux);
   delete h;
   return MIQR_OK;
 }
@@ -694,7 +569,27 @@ const char* miqr_last_error(miqr_handle h) { return h ? h->err.c_str() : ""; }
 
 int64_t qr_workspace_size(int64_t m, int64_t n, const qr_opts* o) {
   if (m < n || n < 1) return 0;
-  return factor_layout(m, n, tuning_from(o, m, n)).total * (int64_t)sizeof(double);
+  if (check_opts(nullptr, m, o) != MIQR_OK) return 0;
+  const Tuning t = choose_tuning(m, n, o);
+  return factor_layout(m, n, t, o && o->Q).total * (int64_t)sizeof(double);
+}
+
+int64_t qr_t_rows(int64_t m, int64_t n, const qr_opts* o) {
+  if (m < n || n < 1) return 0;
+  if (check_opts(nullptr, m, o) != MIQR_OK) return 0;
+  return t_rows(choose_tuning(m, n, o), n);
+}
+
+int64_t qr_plan(int64_t m, int64_t n, const qr_opts* o, int lstsq, char* buf, int64_t len) {
+  if (m < n || n < 1) return -1;
+  if (check_opts(nullptr, m, o) != MIQR_OK) return -1;
+  const std::string d = describe_plan(m, n, choose_tuning(m, n, o, lstsq != 0));
+  if (buf && len > 0) {
+    const size_t c = std::min<size_t>(d.size(), (size_t)len - 1);
+    std::memcpy(buf, d.data(), c);
+    buf[c] = 0;
+  }
+  return (int64_t)d.size();
 }
 
 double miqr_last_gemm_flops(miqr_handle h) { return h ? h->gemm_flops : 0.0; }
@@ -736,22 +631,31 @@ miqr_status qr_factor(miqr_handle h, void* stream, int64_t m, int64_t n, double*
   ProfScope prof_scope(h);
   h->err.clear();
   if (n < 1 || m < n) return fail(h, MIQR_EINVAL, "need m >= n >= 1");
-  if (lda < m || ldt < n) return fail(h, MIQR_EINVAL, "leading dimension too small");
+  if (lda < m) return fail(h, MIQR_EINVAL, "leading dimension too small");
   if (bad_ptr(A) || bad_ptr(T)) return fail(h, MIQR_EINVAL, "null matrix pointer");
-  int prec = o ? o->precision : MIQR_FP64;
-  if (prec != MIQR_FP64 && prec != MIQR_MIXED_FP32 && prec != MIQR_MIXED_BF16)
-    return fail(h, MIQR_EINVAL, "bad precision");
-  if (o && (o->b < 0 || o->b > kNB)) return fail(h, MIQR_EINVAL, "b must be in [0, 64]");
-  if (o && o->leaf_rows != 0 && o->leaf_rows != 128 && o->leaf_rows != 256)
-    return fail(h, MIQR_EINVAL, "leaf_rows must be 0, 128 or 256");
-  if (o && (o->chain < 0 || o->arity < 0 || o->arity == 1))
-    return fail(h, MIQR_EINVAL, "chain must be >= 0 and arity 0 or >= 2");
-  if (o && o->normalize && !o->sign_out) return fail(h, MIQR_EINVAL, "normalize needs sign_out");
-  if (o && o->Q && o->ldq < m) return fail(h, MIQR_EINVAL, "ldq < m");
+  miqr_status st = check_opts(h, m, o);
+  if (st != MIQR_OK) return st;
+  const Tuning tune = tuning_for(h, m, n, o, false);
+  if (ldt < t_rows(tune, n))
+    return fail(h, MIQR_EINVAL, "ldt < " + std::to_string(t_rows(tune, n)) + " (rows of T)");
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
-  const int comp = prec == MIQR_MIXED_FP32 ? COMPUTE_F32
-                   : prec == MIQR_MIXED_BF16 ? COMPUTE_BF16 : COMPUTE_F64;
-  return do_factor(h, (hipStream_t)stream, m, n, A, lda, T, ldt, o, comp);
+  const int prec = o ? o->precision : MIQR_FP64;
+  FactorArgs a;
+  a.m = m;
+  a.n = n;
+  a.A = A;
+  a.lda = lda;
+  a.T = T;
+  a.ldt = ldt;
+  a.update_compute = prec == MIQR_MIXED_FP32 ? COMPUTE_F32
+                     : prec == MIQR_MIXED_BF16 ? COMPUTE_BF16 : COMPUTE_F64;
+  if (o) {
+    a.Q = o->Q;
+    a.ldq = o->ldq;
+    a.normalize = o->normalize;
+    a.sign = o->sign_out;
+  }
+  return do_factor(h, (hipStream_t)stream, tune, a);
 }
 
 miqr_status qr_apply_q(miqr_handle h, void* stream, char trans, int64_t m, int64_t n, int64_t k,
@@ -772,8 +676,38 @@ miqr_status qr_apply_q(miqr_handle h, void* stream, char trans, int64_t m, int64
   double* W1 = ar.take(n * k);
   double* W2 = ar.take(n * k);
   double* sc = ar.take(scratch_n);
-  return do_apply(h, (hipStream_t)stream, trans, m, n, k, VR, lda, T, ldt, C, ldc, W1, W2, sc,
-                  scratch_n);
+  hipError_t e = apply_q_full((hipStream_t)stream, trans, m, n, k, VR, lda, T, ldt, C, ldc, W1, W2,
+                              sc, scratch_n);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "qr_apply_q");
+  return MIQR_OK;
+}
+
+miqr_status qr_apply_q_blocked(miqr_handle h, void* stream, char trans, int64_t m, int64_t n,
+                               int64_t k, const double* VR, int64_t lda, const double* T,
+                               int64_t ldt, int64_t nb, double* C, int64_t ldc) {
+  if (!h) return MIQR_EINVAL;
+  ProfScope prof_scope(h);
+  h->err.clear();
+  if (trans != 'N' && trans != 'T') return fail(h, MIQR_EINVAL, "trans must be 'N' or 'T'");
+  if (n < 1 || m < n || k < 0 || nb < 1) return fail(h, MIQR_EINVAL, "need m >= n >= 1, k >= 0, nb >= 1");
+  if (lda < m || ldt < std::min(nb, n) || ldc < m)
+    return fail(h, MIQR_EINVAL, "leading dimension too small");
+  if (bad_ptr(VR) || bad_ptr(T) || bad_ptr(C)) return fail(h, MIQR_EINVAL, "null pointer");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
+  const int64_t w = std::min(nb, n);
+  const int64_t scratch_n = std::max<int64_t>(int64_t(4) << 20, 4 * w * k);
+  miqr_status st = ensure_ws(h, (size_t)(2 * w * k + scratch_n + 128) * sizeof(double));
+  if (st != MIQR_OK) return st;
+  Arena ar{(double*)h->ws};
+  double* W1 = ar.take(w * k);
+  double* W2 = ar.take(w * k);
+  double* sc = ar.take(scratch_n);
+  hipError_t e = apply_q_blocked((hipStream_t)stream, trans, m, n, k, VR, lda, T, ldt, nb, C, ldc,
+                                 W1, W2, sc, scratch_n);
+  if (e == hipSuccess) e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "qr_apply_q_blocked");
+  return MIQR_OK;
 }
 
 miqr_status qr_form_q(miqr_handle h, void* stream, int64_t m, int64_t n, const double* VR,
@@ -781,6 +715,7 @@ miqr_status qr_form_q(miqr_handle h, void* stream, int64_t m, int64_t n, const d
                       int64_t ldq) {
   if (!h) return MIQR_EINVAL;
   ProfScope prof_scope(h);
+  h->err.clear();
   if (n < 1 || m < n) return fail(h, MIQR_EINVAL, "need m >= n >= 1");
   if (lda < m || ldt < n || ldq < m) return fail(h, MIQR_EINVAL, "leading dimension too small");
   if (bad_ptr(VR) || bad_ptr(T) || bad_ptr(Q)) return fail(h, MIQR_EINVAL, "null pointer");
@@ -788,13 +723,8 @@ miqr_status qr_form_q(miqr_handle h, void* stream, int64_t m, int64_t n, const d
   hipStream_t s = (hipStream_t)stream;
   // Q = [I; 0] - V (T V_top^T), V_top the unit lower n x n top of V.
   const int64_t scratch_n = std::max<int64_t>(int64_t(4) << 20, 2 * n * n);
-  // The workspace may already be in use by a qr_factor on this stream; place W
-  // after the factorisation's region by sizing for both.
-  const size_t need = (size_t)(n * n + scratch_n + 64) * sizeof(double);
-  if (need > h->ws_bytes) {
-    miqr_status st = ensure_ws(h, need);
-    if (st != MIQR_OK) return st;
-  }
+  miqr_status st = ensure_ws(h, (size_t)(n * n + scratch_n + 64) * sizeof(double));
+  if (st != MIQR_OK) return st;
   Arena ar{(double*)h->ws};
   double* W = ar.take(n * n);
   double* sc = ar.take(scratch_n);
@@ -840,6 +770,38 @@ miqr_status qr_solve_r(miqr_handle h, void* stream, int64_t n, int64_t nrhs, con
   return MIQR_OK;
 }
 
+miqr_status qr_backward_error(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t nrhs,
+                              const double* A, int64_t lda, const double* B, int64_t ldb,
+                              const double* X, int64_t ldx, double* beta) {
+  if (!h) return MIQR_EINVAL;
+  ProfScope prof_scope(h);
+  h->err.clear();
+  if (n < 1 || m < n || nrhs < 1) return fail(h, MIQR_EINVAL, "need m >= n >= 1, nrhs >= 1");
+  if (lda < m || ldb < m || ldx < n) return fail(h, MIQR_EINVAL, "leading dimension too small");
+  if (bad_ptr(A) || bad_ptr(B) || bad_ptr(X) || bad_ptr(beta))
+    return fail(h, MIQR_EINVAL, "null pointer");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
+  const int64_t scn = int64_t(4) << 20;
+  double *Rr = nullptr, *U = nullptr, *nrm = nullptr, *sc = nullptr;
+  auto carve = [&](Arena& ar) {
+    Rr = ar.take(m * nrhs);
+    U = ar.take(n * nrhs);
+    nrm = ar.take(3 * nrhs + n + 8);
+    sc = ar.take(scn);
+  };
+  Arena dry{nullptr};
+  carve(dry);
+  miqr_status st = ensure_ws(h, (size_t)dry.off * sizeof(double));
+  if (st != MIQR_OK) return st;
+  Arena ar{(double*)h->ws};
+  carve(ar);
+  hipError_t e = hipSuccess;
+  backward_error_dev((hipStream_t)stream, m, n, nrhs, A, lda, B, ldb, X, ldx, Rr, U, nrm, sc, scn,
+                     &e, beta);
+  if (e != hipSuccess) return hip_fail(h, e, "qr_backward_error");
+  return MIQR_OK;
+}
+
 miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t nrhs, double* A,
                      int64_t lda, double* B, int64_t ldb, const qr_opts* o, qr_info* info) {
   if (!h) return MIQR_EINVAL;
@@ -851,96 +813,55 @@ miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t 
   const int prec = o ? o->precision : MIQR_FP64;
   if (prec != MIQR_FP64 && prec != MIQR_MIXED_FP32 && prec != MIQR_MIXED_BF16)
     return fail(h, MIQR_EINVAL, "bad precision");
-  if (o && (o->b < 0 || o->b > kNB)) return fail(h, MIQR_EINVAL, "b must be in [0, 64]");
   if (o && (o->normalize || o->Q)) return fail(h, MIQR_ENOTSUP, "lstsq takes no Q/normalize");
+  miqr_status cst = check_opts(h, m, o);
+  if (cst != MIQR_OK) return cst;
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   if (info) std::memset(info, 0, sizeof(*info));
   if (prec != MIQR_FP64) {
     const int comp = prec == MIQR_MIXED_FP32 ? COMPUTE_F32 : COMPUTE_BF16;
-    miqr_status st = lstsq_mixed(h, s, m, n, nrhs, A, lda, B, ldb, o, comp, info);
-      return st;
+    return lstsq_mixed(h, s, m, n, nrhs, A, lda, B, ldb, o, comp, info);
   }
 
-  // Layout: factorisation workspace first, then T, W1, W2, and (for info) copies.
-  const Tuning tune = tuning_from(o, m, n);
-  FactorLayout L = factor_layout(m, n, tune);
+  // Layout: the factorisation's regions first, then T, W1, W2, and (for
+  // info) the originals and the residual.
+  const Tuning tune = tuning_for(h, m, n, o, true);
+  const FactorLayout L = factor_layout(m, n, tune);
+  const int64_t tr = t_rows(tune, n);
+  FactorWs f;
   double *T = nullptr, *W1 = nullptr, *W2 = nullptr;
-  double *A0 = nullptr, *B0 = nullptr, *nrm = nullptr;
-  auto carve = [&](Arena& ar) {
-    ar.take(L.total);
-    T = ar.take(n * n);
+  double *A0 = nullptr, *B0 = nullptr, *Rr = nullptr, *nrm = nullptr;
+  auto carve = [&](double* base) {
+    f = carve_factor(base, L);
+    Arena ar{base};
+    ar.off = f.doubles;
+    T = ar.take(tr * n);
     W1 = ar.take(n * nrhs);
     W2 = ar.take(n * nrhs);
     if (info) {
       A0 = ar.take(m * n);
       B0 = ar.take(m * nrhs);
+      Rr = ar.take(m * nrhs);
       nrm = ar.take(3 * nrhs + n + 8);
     }
+    return ar.off;
   };
-  Arena dry{nullptr};
-  carve(dry);
-  miqr_status st = ensure_ws(h, (size_t)dry.off * sizeof(double));
+  const int64_t need = carve(nullptr);
+  miqr_status st = ensure_ws(h, (size_t)need * sizeof(double));
   if (st != MIQR_OK) return st;
-  Arena ar{(double*)h->ws};
-  carve(ar);
+  carve((double*)h->ws);
   if (info) {
     copy_matrix(s, m, n, A, lda, A0, m);
     copy_matrix(s, m, nrhs, B, ldb, B0, m);
   }
-  // The factorisation uses the front of the workspace (do_factor re-derives
-  // the same layout, so the regions above stay untouched).
-  st = do_factor(h, s, m, n, A, lda, T, n, o, COMPUTE_F64, true);
+  st = lstsq_core(h, s, tune, f, m, n, nrhs, A, lda, B, ldb, T, W1, W2, info);
   if (st != MIQR_OK) return st;
-  // The factorisation's split-K scratch (same arena layout as do_factor) is free now.
-  Arena far{(double*)h->ws};
-  far.take(L.tsqr);
-  far.take(L.wa);
-  far.take(L.wb);
-  double* sc = far.take(L.scratch);
-  st = apply_qt_spine(h, s, m, n, nrhs, A, lda, T, n, B, ldb, tune.b, W1, W2, sc, L.scratch);
-  if (st != MIQR_OK) return st;
-  find_zero_diagonal(s, n, A, lda, h->dflag);
-  int flag = 0;
-  hipError_t e = hipMemcpyAsync(&flag, h->dflag, sizeof(int), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq");
-  if (flag) {
-    if (info) info->singular_index = flag;
-    return fail(h, MIQR_ESINGULAR, "R(" + std::to_string(flag - 1) + ") == 0");
-  }
-  e = solve_upper(s, n, nrhs, A, lda, B, ldb, sc, L.scratch);
-  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq solve");
   if (info) {
-    info->precision_used = MIQR_FP64;
-    // r = b - A x (into B0), g = A^T r (into W1), norms.
-    GemmDesc d;
-    d.ta = 'N'; d.tb = 'N'; d.M = m; d.N = nrhs; d.K = n; d.alpha = -1.0; d.beta = 1.0;
-    d.A = A0; d.lda = m; d.B = B; d.ldb = ldb; d.C = B0; d.ldc = m;
-    e = gemm(d, s, sc, L.scratch);
-    d = GemmDesc();
-    d.ta = 'T'; d.tb = 'N'; d.M = n; d.N = nrhs; d.K = m;
-    d.A = A0; d.lda = m; d.B = B0; d.ldb = m; d.C = W1; d.ldc = n;
-    if (e == hipSuccess) e = gemm(d, s, sc, L.scratch);
-    if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq residual");
-    column_sumsq(s, m, nrhs, B0, m, nrm);              // ||r||^2
-    column_sumsq(s, n, nrhs, W1, n, nrm + nrhs);       // ||A^T r||^2
-    column_sumsq(s, n, nrhs, B, ldb, nrm + 2 * nrhs);  // ||x||^2
-    column_sumsq(s, m, n, A0, m, nrm + 3 * nrhs);      // column norms of A
-    std::vector<double> hn(3 * nrhs + n);
-    e = hipMemcpyAsync(hn.data(), nrm, sizeof(double) * hn.size(), hipMemcpyDeviceToHost, s);
-    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    hipError_t e = hipSuccess;
+    info->backward_error = backward_error_dev(s, m, n, nrhs, A0, m, B0, m, B, ldb, Rr, W1, nrm,
+                                              f.scratch, f.scratch_n, &e);
     if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq info");
-    double fa = 0.0;
-    for (int64_t j = 0; j < n; ++j) fa += hn[3 * nrhs + j];
-    fa = std::sqrt(fa);
-    double worst = 0.0;
-    for (int64_t c = 0; c < nrhs; ++c) {
-      const double rn = std::sqrt(hn[c]), gn = std::sqrt(hn[nrhs + c]), xn = std::sqrt(hn[2 * nrhs + c]);
-      const double den = fa * (fa * xn + rn);
-      worst = std::max(worst, den > 0 ? gn / den : 0.0);
-    }
-    info->backward_error = worst;
   }
   return MIQR_OK;
 }

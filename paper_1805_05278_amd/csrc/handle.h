@@ -5,9 +5,24 @@
 #include <string>
 #include <vector>
 
+#include <map>
+#include <tuple>
+
 #include "batched.h"
 #include "miqr.h"
+#include "plan.h"
 #include "profiler.h"
+
+// Key of the handle's tuning cache: the shape and every option the cost model
+// reads.
+struct TuneKey {
+  int64_t m, n, lstsq, b, bstar, nb, leaf_rows, chain, arity, layout, nola;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(m, n, lstsq, b, bstar, nb, leaf_rows, chain, arity, layout, nola) <
+           std::tie(o.m, o.n, o.lstsq, o.b, o.bstar, o.nb, o.leaf_rows, o.chain, o.arity,
+                    o.layout, o.nola);
+  }
+};
 
 struct miqr_ctx {
   int device = 0;
@@ -25,4 +40,10 @@ struct miqr_ctx {
   int32_t* pin_status = nullptr;
   int64_t pin_cap = 0;
   hipEvent_t table_ev = nullptr;
+  // Look-ahead of the right-looking top level: a second stream (default
+  // priority) and the two events that order it against the caller's stream.
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_panel = nullptr;
+  hipEvent_t ev_update = nullptr;
+  std::map<TuneKey, miqr::Tuning> tune_cache;
 };

@@ -5,8 +5,9 @@
 
 namespace miqr {
 
-// Zero the strict lower triangle of an n x n matrix.
-void zero_strict_lower(hipStream_t s, int64_t n, double* T, int64_t ldt);
+// Zero the strict lower triangle of each nb x nb diagonal block of a matrix
+// with n columns (nb = n: the strict lower triangle of an n x n matrix).
+void zero_block_lower(hipStream_t s, int64_t n, int64_t nb, double* T, int64_t ldt);
 // Q = [I_n; 0] (m x n).
 void set_identity(hipStream_t s, int64_t m, int64_t n, double* Q, int64_t ldq);
 // Copy an m x n matrix.
@@ -18,8 +19,9 @@ void scale_columns(hipStream_t s, int64_t m, int64_t n, double* Q, int64_t ldq, 
 // (+1 for >= 0); d is written to `sign`.
 void normalize_r(hipStream_t s, int64_t n, double* A, int64_t lda, double* sign);
 // For m == n: switch the last reflector from tau = 2 to tau = 0 (negate
-// R_{n-1,n-1}, zero T[:, n-1]).
-void square_last_column(hipStream_t s, int64_t n, double* A, int64_t lda, double* T, int64_t ldt);
+// R_{n-1,n-1}, zero the trows entries of T's last column at Tcol).
+void square_last_column(hipStream_t s, int64_t n, double* A, int64_t lda, double* Tcol,
+                        int64_t trows);
 // *flag = smallest 1-based j with R_jj == 0 (or 0); flag is device memory.
 void find_zero_diagonal(hipStream_t s, int64_t n, const double* R, int64_t ldr, int* flag);
 // X <- R^{-1} X for the n x n upper triangle of R, blocked back substitution.

@@ -13,41 +13,43 @@ static inline unsigned nblocks_for(int64_t n, int per = 256, int64_t cap = 65536
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + per - 1) / per, cap));
 }
 
-__global__ void k_zero_strict_lower(int64_t n, double* T, int64_t ldt) {
-  const int64_t total = n * n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % n, j = e / n;
-    if (i > j) T[i + j * ldt] = 0.0;
+// Elementwise kernels over an m x n column-major matrix: blockIdx.y walks the
+// columns and blockIdx.x the rows, so no thread divides a flat index.
+struct Grid2 {
+  dim3 g;
+  Grid2(int64_t m, int64_t n) {
+    const int64_t gx = std::max<int64_t>(1, std::min<int64_t>((m + 255) / 256, 256));
+    const int64_t gy = std::max<int64_t>(1, std::min<int64_t>(n, 4096));
+    g = dim3((unsigned)gx, (unsigned)gy);
+  }
+};
+#define MIQR_FOR_ELEMENTS(m, n)                                                    \
+  for (int64_t j = blockIdx.y; j < (n); j += gridDim.y)                           \
+    for (int64_t i = blockIdx.x * 256 + (int64_t)threadIdx.x; i < (m);            \
+         i += (int64_t)gridDim.x * 256)
+
+// Strict lower triangle of the nb x nb diagonal blocks of a matrix with n
+// columns (nb = n: of the whole n x n matrix), rows below nb untouched.
+__global__ __launch_bounds__(256) void k_zero_block_lower(int64_t n, int64_t nb, double* T,
+                                                          int64_t ldt) {
+  MIQR_FOR_ELEMENTS(nb, n) {
+    if (i > j % nb) T[i + j * ldt] = 0.0;
   }
 }
 
-__global__ void k_set_identity(int64_t m, int64_t n, double* Q, int64_t ldq) {
-  const int64_t total = m * n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % m, j = e / m;
-    Q[i + j * ldq] = (i == j) ? 1.0 : 0.0;
-  }
+__global__ __launch_bounds__(256) void k_set_identity(int64_t m, int64_t n, double* Q,
+                                                      int64_t ldq) {
+  MIQR_FOR_ELEMENTS(m, n) { Q[i + j * ldq] = (i == j) ? 1.0 : 0.0; }
 }
 
-__global__ void k_copy_matrix(int64_t m, int64_t n, const double* X, int64_t ldx, double* Y,
-                              int64_t ldy) {
-  const int64_t total = m * n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % m, j = e / m;
-    Y[i + j * ldy] = X[i + j * ldx];
-  }
+__global__ __launch_bounds__(256) void k_copy_matrix(int64_t m, int64_t n, const double* X,
+                                                     int64_t ldx, double* Y, int64_t ldy) {
+  MIQR_FOR_ELEMENTS(m, n) { Y[i + j * ldy] = X[i + j * ldx]; }
 }
 
-__global__ void k_scale_columns(int64_t m, int64_t n, double* Q, int64_t ldq, const double* d) {
-  const int64_t total = m * n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % m, j = e / m;
-    Q[i + j * ldq] *= d[j];
-  }
+__global__ __launch_bounds__(256) void k_scale_columns(int64_t m, int64_t n, double* Q,
+                                                       int64_t ldq, const double* d) {
+  MIQR_FOR_ELEMENTS(m, n) { Q[i + j * ldq] *= d[j]; }
 }
 
 __global__ void k_normalize_r(int64_t n, double* A, int64_t lda, double* sign) {
@@ -65,12 +67,13 @@ __global__ void k_normalize_r(int64_t n, double* A, int64_t lda, double* sign) {
 // reconstruction always reflects there (tau = 2, H = diag(1, .., 1, -1)); the
 // reflector rule of the representation does not (tau = 0, H = I).  Switching
 // to tau = 0 negates the last row of R (only its diagonal entry) and zeroes
-// the last column of T.
-__global__ void k_square_last_column(int64_t n, double* A, int64_t lda, double* T, int64_t ldt) {
-  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+// the last column of T (its trows entries at Tcol).
+__global__ void k_square_last_column(int64_t n, double* A, int64_t lda, double* Tcol,
+                                     int64_t trows) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < trows;
        i += (int64_t)gridDim.x * blockDim.x) {
-    T[i + (n - 1) * ldt] = 0.0;
-    if (i == n - 1) A[(n - 1) + (n - 1) * lda] = -A[(n - 1) + (n - 1) * lda];
+    Tcol[i] = 0.0;
+    if (i == trows - 1) A[(n - 1) + (n - 1) * lda] = -A[(n - 1) + (n - 1) * lda];
   }
 }
 
@@ -139,62 +142,62 @@ static inline unsigned trsm_groups(int64_t nrhs) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((nrhs + 3) / 4, 4096));
 }
 
-__global__ void k_axpy_cols(int64_t rows, int64_t ncols, double sgn, const double* a,
-                            const double* X, int64_t ldx, double* Y, int64_t ldy) {
-  const int64_t total = rows * ncols;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % rows, c = e / rows;
-    Y[i + c * ldy] += sgn * a[c] * X[i + c * ldx];
-  }
+__global__ __launch_bounds__(256) void k_axpy_cols(int64_t rows, int64_t ncols, double sgn,
+                                                   const double* a, const double* X,
+                                                   int64_t ldx, double* Y, int64_t ldy) {
+  MIQR_FOR_ELEMENTS(rows, ncols) { Y[i + j * ldy] += sgn * a[j] * X[i + j * ldx]; }
 }
 
-__global__ void k_xpby_cols(int64_t rows, int64_t ncols, const double* S, int64_t lds,
-                            const double* b, double* P, int64_t ldp) {
-  const int64_t total = rows * ncols;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t i = e % rows, c = e / rows;
-    P[i + c * ldp] = S[i + c * lds] + b[c] * P[i + c * ldp];
-  }
+__global__ __launch_bounds__(256) void k_xpby_cols(int64_t rows, int64_t ncols, const double* S,
+                                                   int64_t lds, const double* b, double* P,
+                                                   int64_t ldp) {
+  MIQR_FOR_ELEMENTS(rows, ncols) { P[i + j * ldp] = S[i + j * lds] + b[j] * P[i + j * ldp]; }
 }
 
 void axpy_cols(hipStream_t s, int64_t rows, int64_t ncols, double sgn, const double* a,
                const double* X, int64_t ldx, double* Y, int64_t ldy) {
-  hipLaunchKernelGGL(k_axpy_cols, dim3(nblocks_for(rows * ncols)), dim3(256), 0, s, rows, ncols,
-                     sgn, a, X, ldx, Y, ldy);
+  if (rows <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_axpy_cols, Grid2(rows, ncols).g, dim3(256), 0, s, rows, ncols, sgn, a, X,
+                     ldx, Y, ldy);
 }
 
 void xpby_cols(hipStream_t s, int64_t rows, int64_t ncols, const double* S, int64_t lds,
                const double* b, double* P, int64_t ldp) {
-  hipLaunchKernelGGL(k_xpby_cols, dim3(nblocks_for(rows * ncols)), dim3(256), 0, s, rows, ncols,
-                     S, lds, b, P, ldp);
+  if (rows <= 0 || ncols <= 0) return;
+  hipLaunchKernelGGL(k_xpby_cols, Grid2(rows, ncols).g, dim3(256), 0, s, rows, ncols, S, lds, b,
+                     P, ldp);
 }
 
-void zero_strict_lower(hipStream_t s, int64_t n, double* T, int64_t ldt) {
-  hipLaunchKernelGGL(k_zero_strict_lower, dim3(nblocks_for(n * n)), dim3(256), 0, s, n, T, ldt);
+void zero_block_lower(hipStream_t s, int64_t n, int64_t nb, double* T, int64_t ldt) {
+  if (n <= 0 || nb <= 0) return;
+  TimedLaunch tl(s, "zero_block_lower", 4.0 * (double)nb * n, 0.0);
+  hipLaunchKernelGGL(k_zero_block_lower, Grid2(nb, n).g, dim3(256), 0, s, n, nb, T, ldt);
 }
 
 void set_identity(hipStream_t s, int64_t m, int64_t n, double* Q, int64_t ldq) {
-  hipLaunchKernelGGL(k_set_identity, dim3(nblocks_for(m * n)), dim3(256), 0, s, m, n, Q, ldq);
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_set_identity, Grid2(m, n).g, dim3(256), 0, s, m, n, Q, ldq);
 }
 
 void copy_matrix(hipStream_t s, int64_t m, int64_t n, const double* X, int64_t ldx, double* Y,
                  int64_t ldy) {
-  hipLaunchKernelGGL(k_copy_matrix, dim3(nblocks_for(m * n)), dim3(256), 0, s, m, n, X, ldx, Y,
-                     ldy);
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_copy_matrix, Grid2(m, n).g, dim3(256), 0, s, m, n, X, ldx, Y, ldy);
 }
 
 void scale_columns(hipStream_t s, int64_t m, int64_t n, double* Q, int64_t ldq, const double* d) {
-  hipLaunchKernelGGL(k_scale_columns, dim3(nblocks_for(m * n)), dim3(256), 0, s, m, n, Q, ldq, d);
+  if (m <= 0 || n <= 0) return;
+  hipLaunchKernelGGL(k_scale_columns, Grid2(m, n).g, dim3(256), 0, s, m, n, Q, ldq, d);
 }
 
 void normalize_r(hipStream_t s, int64_t n, double* A, int64_t lda, double* sign) {
   hipLaunchKernelGGL(k_normalize_r, dim3(nblocks_for(n)), dim3(256), 0, s, n, A, lda, sign);
 }
 
-void square_last_column(hipStream_t s, int64_t n, double* A, int64_t lda, double* T, int64_t ldt) {
-  hipLaunchKernelGGL(k_square_last_column, dim3(nblocks_for(n)), dim3(256), 0, s, n, A, lda, T, ldt);
+void square_last_column(hipStream_t s, int64_t n, double* A, int64_t lda, double* Tcol,
+                        int64_t trows) {
+  hipLaunchKernelGGL(k_square_last_column, dim3(nblocks_for(trows)), dim3(256), 0, s, n, A, lda,
+                     Tcol, trows);
 }
 
 void find_zero_diagonal(hipStream_t s, int64_t n, const double* R, int64_t ldr, int* flag) {

@@ -35,6 +35,7 @@
 #include "common.h"
 #include "profiler.h"
 #include "tsqr.h"
+#include "plan.h"
 
 namespace miqr {
 
@@ -1502,18 +1503,8 @@ TsqrPlan tsqr_plan(int64_t rows, int nbr, int leaf_rows, int chain, int arity, d
   TsqrPlan p;
   p.rows = rows;
   p.nbr = nbr;
-  if (leaf_rows != 128 && leaf_rows != 256) leaf_rows = (rows >= 256 * 64) ? 256 : 128;
-  p.leaf_rows = leaf_rows;
-  const int64_t P0 = std::max<int64_t>(1, (rows + leaf_rows - 1) / leaf_rows);
-  // Chains long enough to leave about 512 of them (two workgroups per CU for
-  // the stacked-block launch), at most eight blocks: measured best at 2^18
-  // rows (chain 2) and 2^20 rows (chain 8).  Longer chains starve that launch
-  // of workgroups; shorter ones add tree levels.
-  if (chain <= 0) chain = (int)std::max<int64_t>(1, std::min<int64_t>(8, P0 / 512));
-  // A node stacks arity - 1 child R factors (nbr rows each) in kYL rows.
-  const int max_arity = 1 + kYL / std::max(nbr, 1);
-  if (arity < 2) arity = std::min(max_arity, 5);
-  arity = std::min(arity, max_arity);
+  const TsqrGeom g = tsqr_geometry(rows, nbr, leaf_rows, chain, arity);
+  p.leaf_rows = g.leaf_rows;
   int64_t off = 0;
   auto take = [&](int64_t n) {
     double* ptr = ws ? ws + off : nullptr;
@@ -1521,15 +1512,15 @@ TsqrPlan tsqr_plan(int64_t rows, int nbr, int leaf_rows, int chain, int arity, d
     return ptr;
   };
   TsqrLevel l0;
-  l0.nblocks = (int)P0;
-  l0.chain_len = chain;
-  l0.nchains = (int)((P0 + chain - 1) / chain);
+  l0.nblocks = (int)g.blocks;
+  l0.chain_len = g.chain;
+  l0.nchains = (int)g.chains;
   p.levels.push_back(l0);
-  while (p.levels.back().nchains > 1 && (int)p.levels.size() < kMaxLevels) {
+  for (int l = 0; l < g.levels; ++l) {
     TsqrLevel lv;
     lv.nblocks = p.levels.back().nchains;
-    lv.chain_len = arity;
-    lv.nchains = (lv.nblocks + arity - 1) / arity;
+    lv.chain_len = g.arity;
+    lv.nchains = (lv.nblocks + g.arity - 1) / g.arity;
     p.levels.push_back(lv);
   }
   for (size_t i = 0; i < p.levels.size(); ++i) {

@@ -2,8 +2,11 @@
 whole matrix in seconds.
 
 Checks that hold at any size, computed on the host in FP64 from the inputs:
- * the leading 128 columns of R equal the oracle's R of A[:, :128] (QR of a
-   leading column block is the leading block of the QR), after D-normalisation;
+ * the leading 1024 columns of R, V and T equal the oracle's factors of
+   A[:, :1024] (the QR of a leading column block is the leading block of the
+   QR: reflectors 0..1023 and the leading 1024 x 1024 block of T depend on
+   those columns only), with the G5 gates and the elementwise gates of the
+   parity tests;
  * sampled entries of R^T R equal the matching inner products a_i^T a_j;
  * G1 probe ||A z - Q (R z)|| / (||A||_F ||z||) <= 1e-13 and G2 probe
    ||Q^T (Q Z) - Z|| / ||Z|| <= 1e-13 on random Z (8 columns);
@@ -15,6 +18,7 @@ import pytest
 
 import oracle
 import synth
+from tests.test_gpu_parity import check_against_oracle, rel
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -36,13 +40,15 @@ def factor_and_check(m_, h, m, n, seed, b=0):
     torch.cuda.synchronize()
     VR = Ad.cpu().numpy()
     R = np.triu(VR[:n, :n])
-    # Leading block against the oracle.
-    k = 128
-    Ro = oracle.qr(np.asfortranarray(A[:, :k]), with_t=False).R
-    Rn, _, _ = oracle.normalize(R[:k, :k])
-    Ron, _, _ = oracle.normalize(Ro)
-    lead = np.linalg.norm(Rn - Ron) / np.linalg.norm(Ron)
-    assert lead <= 1e-13, lead
+    # Leading 1024-column block against the oracle.
+    k = 1024
+    print("oracle of the %dx%d prefix" % (m, k), flush=True)
+    fo = oracle.qr(np.asfortranarray(A[:, :k]))
+    g = {"R": R[:k, :k], "V": np.tril(VR[:, :k], -1) + np.eye(m, k),
+         "T": Td[:k, :k].cpu().numpy()}
+    check_against_oracle(np.asfortranarray(A[:, :k]), g, tol_r=1e-13, tol_vt=1e-12, f=fo)
+    lead = rel(oracle.normalize(g["R"])[0], oracle.normalize(fo.R)[0])
+    del fo, g
     # Sampled Gram identities (RᵀR)_ij = a_i^T a_j.
     r = synth.rng(seed + 1)
     cols = np.linalg.norm(A, axis=0)
