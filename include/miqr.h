@@ -192,6 +192,21 @@ miqr_status qr_factor(miqr_handle handle, void *stream, int64_t m, int64_t n,
                       double *A, int64_t lda, double *T, int64_t ldt,
                       const qr_opts *opts);
 
+/* qr_factor for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Same
+ * arguments, results and errors as qr_factor, but every step runs on the
+ * caller's stream (no look-ahead stream) and the workspace is a static 64 MiB
+ * device array of the library, one per GPU, set up by miqr_create and held
+ * until the process ends; the call allocates nothing.  Shapes whose
+ * workspace does not fit (roughly m x n beyond 4e6 doubles of panel blocks;
+ * qr_workspace_size reports the need without its split-K share) return
+ * MIQR_EINVAL and enqueue nothing.  Every call on one GPU shares that array,
+ * so calls that overlap on one GPU (different streams or threads, any handle)
+ * race and must be ordered by the caller. */
+miqr_status qr_factor_noalloc(miqr_handle handle, void *stream, int64_t m,
+                              int64_t n, double *A, int64_t lda, double *T,
+                              int64_t ldt, const qr_opts *opts);
+
 /* Apply the orthogonal factor from qr_factor (Sec. 2.3, Q = I - V T V^T):
  *   trans 'N': C <- Q C;   trans 'T': C <- Q^T C.
  *   VR (m x n, lda) and T (n x n, ldt) as returned by qr_factor; C is m x k

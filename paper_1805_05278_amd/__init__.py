@@ -94,6 +94,8 @@ def lib():
         L.qr_factor.argtypes = [_vp, _vp, _i64, _i64, _vp, _i64, _vp, _i64,
                                 ctypes.POINTER(QrOpts)]
         L.qr_factor.restype = st
+        L.qr_factor_noalloc.argtypes = L.qr_factor.argtypes
+        L.qr_factor_noalloc.restype = st
         L.qr_apply_q.argtypes = [_vp, _vp, ctypes.c_char, _i64, _i64, _i64, _vp, _i64, _vp,
                                  _i64, _vp, _i64]
         L.qr_apply_q.restype = st
@@ -278,6 +280,15 @@ class Handle:
         m, n = A.shape
         self._check(lib().qr_factor(self._h, _stream(), m, n, ap, lda, tp, ldt,
                                     ctypes.byref(opts) if opts else None))
+
+    def factor_noalloc(self, A, T, opts: Optional[QrOpts] = None):
+        """factor() on the caller's stream in the library's static device
+        workspace (no device allocation)."""
+        ap, lda = _mat(A, "A")
+        tp, ldt = _mat(T, "T")
+        m, n = A.shape
+        self._check(lib().qr_factor_noalloc(self._h, _stream(), m, n, ap, lda, tp, ldt,
+                                            ctypes.byref(opts) if opts else None))
 
     def apply_q(self, trans: str, VR, T, C):
         vp, lda = _mat(VR, "VR")

@@ -15,6 +15,7 @@
 #include "gemm.h"
 #include "handle.h"
 #include "miqr.h"
+#include "noalloc.h"
 #include "plan.h"
 #include "profiler.h"
 #include "solve.h"
@@ -531,6 +532,12 @@ miqr_status miqr_create(miqr_handle* handle, int device) {
     delete c;
     return MIQR_EHIP;
   }
+  // The static workspace of qr_factor_noalloc on this device.
+  if (noalloc_setup(device) != hipSuccess) {
+    hipFree(c->dflag);
+    delete c;
+    return MIQR_EHIP;
+  }
   *handle = c;
   return MIQR_OK;
 }
@@ -656,6 +663,58 @@ miqr_status qr_factor(miqr_handle h, void* stream, int64_t m, int64_t n, double*
     a.sign = o->sign_out;
   }
   return do_factor(h, (hipStream_t)stream, tune, a);
+}
+
+miqr_status qr_factor_noalloc(miqr_handle h, void* stream, int64_t m, int64_t n, double* A,
+                              int64_t lda, double* T, int64_t ldt, const qr_opts* o) {
+  if (!h) return MIQR_EINVAL;
+  ProfScope prof_scope(h);
+  h->err.clear();
+  if (n < 1 || m < n) return fail(h, MIQR_EINVAL, "need m >= n >= 1");
+  if (lda < m) return fail(h, MIQR_EINVAL, "leading dimension too small");
+  if (bad_ptr(A) || bad_ptr(T)) return fail(h, MIQR_EINVAL, "null matrix pointer");
+  miqr_status st = check_opts(h, m, o);
+  if (st != MIQR_OK) return st;
+  // Every step on the caller's stream (no look-ahead stream or events).
+  qr_opts one = o ? *o : qr_opts{};
+  one.no_lookahead = 1;
+  const Tuning tune = tuning_for(h, m, n, &one, false);
+  if (ldt < t_rows(tune, n))
+    return fail(h, MIQR_EINVAL, "ldt < " + std::to_string(t_rows(tune, n)) + " (rows of T)");
+  double* base = noalloc_scratch(h->device);
+  if (!base) return fail(h, MIQR_EHIP, "static workspace not set up on this device");
+  // The regions of the factorisation, with the split-K partials given what
+  // is left of the static array (the products split K only as far as their
+  // partials fit, down to no split at all).
+  FactorLayout L = factor_layout(m, n, tune, one.Q != nullptr);
+  L.total -= ((L.scratch + 31) & ~int64_t(31)) + ((L.scratch_aux + 31) & ~int64_t(31));
+  const int64_t spare = kNoallocDoubles - L.total;
+  if (spare < 2 * 4096)
+    return fail(h, MIQR_EINVAL,
+                "workspace of " + std::to_string((L.total + 2 * 4096) * 8) +
+                    " bytes exceeds the static " + std::to_string(kNoallocDoubles * 8) +
+                    "-byte workspace of qr_factor_noalloc");
+  L.scratch = ((spare / 2) & ~int64_t(31)) - 32;
+  L.scratch_aux = L.scratch;
+  L.total += 2 * (L.scratch + 32);
+  const FactorWs w = carve_factor(base, L);
+  if (w.doubles > kNoallocDoubles) return fail(h, MIQR_EINVAL, "static workspace too small");
+  if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
+  const int prec = one.precision;
+  FactorArgs a;
+  a.m = m;
+  a.n = n;
+  a.A = A;
+  a.lda = lda;
+  a.T = T;
+  a.ldt = ldt;
+  a.update_compute = prec == MIQR_MIXED_FP32 ? COMPUTE_F32
+                     : prec == MIQR_MIXED_BF16 ? COMPUTE_BF16 : COMPUTE_F64;
+  a.Q = one.Q;
+  a.ldq = one.ldq;
+  a.normalize = one.normalize;
+  a.sign = one.sign_out;
+  return factor_with(h, (hipStream_t)stream, tune, w, a);
 }
 
 miqr_status qr_apply_q(miqr_handle h, void* stream, char trans, int64_t m, int64_t n, int64_t k,
