@@ -1,0 +1,210 @@
+"""Measure and fit the library's cost model (the alpha-beta-gamma model of
+Sec. 3 on one GPU: time = sum_i coef_i * feature_i, with the paper's message
+count split by the kind of launch).
+
+    python -m paper_1805_05278_amd.cost_fit sweep -o SWEEP.json [--reps 3]
+        Factor seeded Gaussian matrices over a grid of shapes and tunings on
+        one stream, timing each (minimum over the repetitions), and record
+        the plan the library reports for it (qr_plan: features, predicted
+        seconds).  Runs without look-ahead are the fitting set; runs with it
+        check the model's overlap schedule.
+
+    python -m paper_1805_05278_amd.cost_fit fit SWEEP.json -o FIT.md [--json FIT.json]
+        Fit the coefficients by non-negative least squares on relative error
+        (each run weighted by 1 / measured time) over the runs without
+        look-ahead, and report the fitted model's prediction error on every
+        run beside the prediction of the coefficients the library was built
+        with.
+
+Only the sweep touches the GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(HERE))
+
+FEATURES = ["leaf256_steps", "leaf128_steps", "tree_levels", "tree_levels_small", "hr",
+            "down_levels", "gemm_launches", "gemm_weighted_flops", "panel_bytes"]
+
+TALL = [(1048576, 64), (262144, 64), (65536, 64), (16384, 64), (4096, 64), (262144, 256),
+        (65536, 256), (20000, 640)]
+TALL_TUNINGS = [dict(), dict(leaf_rows=128, chain=1, arity=5), dict(leaf_rows=256, chain=1, arity=5),
+                dict(leaf_rows=256, chain=2, arity=5), dict(leaf_rows=256, chain=8, arity=5),
+                dict(leaf_rows=128, chain=4, arity=3), dict(leaf_rows=128, chain=1, arity=2),
+                dict(leaf_rows=256, chain=4, arity=3), dict(b=32)]
+WIDE = [(65536, 2048), (16384, 4096), (8192, 8192), (4096, 4096), (2048, 2048), (16384, 16384),
+        (65536, 8192)]
+WIDE_TUNINGS = [dict(t_layout=0), dict(t_layout=0, b=32), dict(t_layout=1, nb=128),
+                dict(t_layout=1, nb=256), dict(t_layout=1, nb=512), dict(t_layout=1, nb=1024)]
+
+
+def _label(kw):
+    return ",".join("%s=%s" % kv for kv in sorted(kw.items())) or "auto"
+
+
+def sweep(out, reps, quick=False):
+    import torch
+    import paper_1805_05278_amd as miqr
+    import synth
+
+    h = miqr.Handle(0)
+    runs = []
+    plan_cases = []
+    for (m, n) in TALL:
+        for kw in TALL_TUNINGS:
+            plan_cases.append((m, n, dict(kw), [False]))
+    for (m, n) in WIDE:
+        for kw in WIDE_TUNINGS:
+            la = [False, True] if kw.get("t_layout") == 1 else [False]
+            plan_cases.append((m, n, dict(kw), la))
+    if quick:
+        plan_cases = plan_cases[::4]
+    cur = None
+    for (m, n, kw, las) in plan_cases:
+        if cur is None or cur[0] != (m, n):
+            cur = None
+            torch.cuda.empty_cache()
+            A0 = synth.gaussian_device(m, n, 51000 + m % 997 + n)
+            A = miqr.colmajor(m, n)
+            cur = ((m, n), A0, A)
+        _, A0, A = cur
+        for la in las:
+            o = h.opts(lookahead=la, **kw)
+            plan = h.plan(m, n, o)
+            T = miqr.colmajor(h.t_rows(m, n, o), n)
+            times = []
+            for r in range(reps + 1):
+                A.copy_(A0)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                h.factor(A, T, o)
+                torch.cuda.synchronize()
+                if r:
+                    times.append(time.perf_counter() - t0)
+            rec = {"m": m, "n": n, "tuning_given": _label(kw), "lookahead": la,
+                   "seconds": min(times), "tuning": plan["tuning"], "features": plan["features"],
+                   "predicted": plan["cost"]["seconds"], "coefficients": plan["coefficients"],
+                   "schedule": plan.get("schedule", [])}
+            runs.append(rec)
+            print("%dx%d %-32s la=%d  %.3f ms  predicted %.3f ms" % (
+                m, n, _label(kw), la, rec["seconds"] * 1e3, rec["predicted"] * 1e3), flush=True)
+            del T
+    h.close()
+    with open(out, "w") as f:
+        json.dump({"runs": runs}, f, indent=1)
+
+
+def fit(path, out, out_json=None):
+    import numpy as np
+    from scipy.optimize import nnls
+
+    with open(path) as f:
+        runs = json.load(f)["runs"]
+    fit_set = [r for r in runs if not r["lookahead"]]
+    X = np.array([[r["features"][k] for k in FEATURES] for r in fit_set], dtype=float)
+    y = np.array([r["seconds"] for r in fit_set])
+    # Relative-error weighting: every run counts by its share of error.
+    w = 1.0 / y
+    scale = X.max(axis=0)
+    scale[scale == 0] = 1.0
+    coef_s, _ = nnls((X / scale) * w[:, None], y * w)
+    coef = coef_s / scale
+    pred = X @ coef
+    rel = (pred - y) / y
+    # Look-ahead overlap: the schedule of the right-looking top level,
+    # step k = max(a, b) + rho min(a, b) with a = update of panel k + 1's
+    # columns + factorisation of panel k + 1 and b = the rest of panel k's
+    # update; rho by grid search over the look-ahead runs.
+    la_runs = [r for r in runs if r["lookahead"] and r.get("schedule")]
+
+    def sched(r, rho):
+        S = np.array(r["schedule"])  # panels x 3 x features
+        Fp, Un, Ur = S[:, 0] @ coef, S[:, 1] @ coef, S[:, 2] @ coef
+        t = Fp[0]
+        for k in range(len(Fp) - 1):
+            a, b = Un[k] + Fp[k + 1], Ur[k]
+            t += max(a, b) + rho * min(a, b)
+        return t
+    rho = float("nan")
+    if la_runs:
+        grid = np.linspace(0.0, 1.0, 101)
+        errs = [np.median([abs(sched(r, g) - r["seconds"]) / r["seconds"] for r in la_runs])
+                for g in grid]
+        rho = float(grid[int(np.argmin(errs))])
+    old = np.array([[r["features"][k] for k in FEATURES] for r in fit_set]) @ \
+        np.array([fit_set[0]["coefficients"][k] for k in FEATURES])
+    rel_old = (old - y) / y
+    lines = ["# Cost model fit (one stream, no look-ahead)", "",
+             "time = sum_i coef_i * feature_i; features as qr_plan reports them for the tuning",
+             "run; coefficients by non-negative least squares on relative error over %d runs." %
+             len(fit_set), "",
+             "| feature | fitted coefficient | unit | built-in coefficient |", "|---|---:|---|---:|"]
+    units = {"gemm_weighted_flops": "s per weighted flop (1 / asymptotic rate)",
+             "panel_bytes": "s per byte (1 / bandwidth)"}
+    for k, c in zip(FEATURES, coef):
+        lines.append("| %s | %.4g | %s | %.4g |" % (k, c, units.get(k, "s per count"),
+                                                fit_set[0]["coefficients"][k]))
+    lines += ["", "Asymptotic GEMM rate: %.1f TFLOP/s (weighted by (d + d0)/d, d0 = %g)." % (
+        1e-12 / coef[FEATURES.index("gemm_weighted_flops")] if coef[FEATURES.index("gemm_weighted_flops")] > 0 else float("nan"),
+        fit_set[0]["coefficients"]["d0"]), "",
+        "Relative prediction error over the fitting runs: fitted median |e| %.1f %%, max %.1f %%;"
+        " built-in median %.1f %%, max %.1f %%." % (
+            100 * np.median(np.abs(rel)), 100 * np.max(np.abs(rel)),
+            100 * np.median(np.abs(rel_old)), 100 * np.max(np.abs(rel_old))), "",
+        "| shape | tuning | look-ahead | measured ms | fitted model ms | error | library's prediction ms | error |",
+        "|---|---|---|---:|---:|---:|---:|---:|"]
+    if la_runs:
+        le = [abs(sched(r, rho) - r["seconds"]) / r["seconds"] for r in la_runs]
+        lines.insert(len(lines) - 3, "Look-ahead overlap rho = %.2f (share of the shorter stream that "
+                     "still adds); relative error over the %d look-ahead runs: median %.1f %%, "
+                     "max %.1f %%." % (rho, len(la_runs), 100 * np.median(le), 100 * np.max(le)))
+        lines.insert(len(lines) - 3, "")
+    for r in runs:
+        fv = np.array([r["features"][k] for k in FEATURES])
+        if not r["lookahead"]:
+            p = float(fv @ coef)
+        elif r.get("schedule"):
+            p = sched(r, rho)
+        else:
+            p = float("nan")
+        lines.append("| %dx%d | %s | %s | %.3f | %s | %s | %.3f | %+.1f %% |" % (
+            r["m"], r["n"], r["tuning_given"], "on" if r["lookahead"] else "off",
+            r["seconds"] * 1e3, ("%.3f" % (p * 1e3)) if p == p else "-",
+            ("%+.1f %%" % (100 * (p - r["seconds"]) / r["seconds"])) if p == p else "-",
+            r["predicted"] * 1e3, 100 * (r["predicted"] - r["seconds"]) / r["seconds"]))
+    with open(out, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    if out_json:
+        with open(out_json, "w") as f:
+            rec = {k: float(c) for k, c in zip(FEATURES, coef)}
+            rec["overlap"] = rho
+            json.dump(rec, f, indent=1)
+    print("\n".join(lines[:20]))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    sub = ap.add_subparsers(dest="cmd", required=True)
+    s = sub.add_parser("sweep")
+    s.add_argument("-o", "--out", required=True)
+    s.add_argument("--reps", type=int, default=3)
+    s.add_argument("--quick", action="store_true")
+    f = sub.add_parser("fit")
+    f.add_argument("sweep")
+    f.add_argument("-o", "--out", required=True)
+    f.add_argument("--json")
+    a = ap.parse_args()
+    if a.cmd == "sweep":
+        sweep(a.out, a.reps, a.quick)
+    else:
+        fit(a.sweep, a.out, a.json)
+
+
+if __name__ == "__main__":
+    main()

@@ -127,14 +127,27 @@ struct SliceLoader {
       else S[k + s * dk][i + s * di] = (T)v;
     }
   }
+  // Loads and stores of a slice known to be plain (in range, mask-free).
+  __device__ void load_plain(double (&r)[L]) const {
+#pragma unroll
+    for (int s = 0; s < L; ++s) r[s] = p[s * estride];
+  }
+  template <typename T, int LD, bool TRANS>
+  __device__ void store_plain(T (*S)[LD], const double (&r)[L]) const {
+#pragma unroll
+    for (int s = 0; s < L; ++s) {
+      if (TRANS) S[i + s * di][k + s * dk] = (T)r[s];
+      else S[k + s * dk][i + s * di] = (T)r[s];
+    }
+  }
   __device__ void advance() { p += step; }
 };
 
 // Whether every element of a slice (rows x0 .. x0+BX-1 of op, k0 .. k0+BK-1)
 // is in range and unaffected by the structure mask.
 template <int BX, int BK, bool ALONG_I>
-__device__ __forceinline__ bool slice_is_plain(int64_t x0, int64_t X, int64_t k0, int64_t kend,
-                                               int mask) {
+__host__ __device__ __forceinline__ bool slice_is_plain(int64_t x0, int64_t X, int64_t k0,
+                                                        int64_t kend, int mask) {
   if (x0 + BX > X || k0 + BK > kend) return false;
   // stored row/col ranges
   const int64_t r0 = ALONG_I ? x0 : k0, r1 = ALONG_I ? x0 + BX - 1 : k0 + BK - 1;
@@ -143,6 +156,38 @@ __device__ __forceinline__ bool slice_is_plain(int64_t x0, int64_t X, int64_t k0
   if (mask == MASK_UPPER) return r1 <= c0;      // on or above the diagonal
   (void)r1; (void)c0;
   return true;
+}
+
+// The slabs s (k0 = kbeg + s BK) for which slice_is_plain holds form an
+// interval: the masks cut a half-plane in (row, col), so the plain slabs of
+// one operand are a prefix or a suffix of the full slabs.  Narrows [*lo, *hi)
+// to that interval.
+template <int BX, int BK, bool ALONG_I>
+__host__ __device__ __forceinline__ void plain_slab_range(int64_t x0, int64_t X, int64_t kbeg,
+                                                          int64_t kend, int mask, int* lo,
+                                                          int* hi) {
+  const int64_t nfull = (kend - kbeg) / BK;  // slabs wholly inside [kbeg, kend)
+  int64_t l = *lo, h = min((int64_t)*hi, nfull);
+  if (x0 + BX > X) h = 0;
+  // first slab index with kbeg + s BK >= need, last with kbeg + s BK <= lim
+  auto from = [&](int64_t need) {
+    need -= kbeg;
+    l = max(l, need <= 0 ? (int64_t)0 : (need + BK - 1) / BK);
+  };
+  auto upto = [&](int64_t lim) {
+    lim -= kbeg;
+    h = min(h, lim < 0 ? (int64_t)0 : lim / BK + 1);
+  };
+  if (mask == MASK_UNIT_LOWER) {
+    if (ALONG_I) upto(x0 - BK);  // stored (x, kk): plain iff x0 > k0 + BK - 1
+    else from(x0 + BX);          // stored (kk, x): plain iff k0 > x0 + BX - 1
+  } else if (mask == MASK_UPPER) {
+    if (ALONG_I) from(x0 + BX - 1);  // plain iff x0 + BX - 1 <= k0
+    else upto(x0 - BK + 1);          // plain iff k0 + BK - 1 <= x0
+  }
+  if (l > h) l = h;
+  *lo = (int)l;
+  *hi = (int)h;
 }
 
 template <int BM, int BN, bool TA, bool TB, int CMP>
@@ -192,16 +237,31 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     lb.advance();
   };
 
+  // Slabs [s1, s2) are plain for both operands: they are loaded and staged
+  // without per-element range and mask selects.  The others (a prefix and a
+  // suffix: the slabs that meet a structure mask, the ragged last slab, and
+  // every slab of a tile that crosses the matrix edge) take the checked
+  // path.  Each loop below prefetches the slab after the current one with the
+  // path that slab needs, so no loaded value is merged across paths.
+  int s1 = 0, s2 = nslab;
+  plain_slab_range<BM, BK, A_ALONG>(i0, g.M, kbeg, kend, g.maskA, &s1, &s2);
+  plain_slab_range<BN, BK, B_ALONG>(j0, g.N, kbeg, kend, g.maskB, &s1, &s2);
   if (nslab > 0) {
-    fetch(kbeg);
-    la.template store_masked<T, BM + PAD, false>(As[0], ra, pa, i0, g.M, kf, kend, g.maskA);
-    lb.template store_masked<T, BN + PAD, false>(Bs[0], rb, pb, j0, g.N, kf, kend, g.maskB);
+    if (s1 == 0 && s2 > 0) {
+      la.load_plain(ra);
+      lb.load_plain(rb);
+      la.advance();
+      lb.advance();
+      la.template store_plain<T, BM + PAD, false>(As[0], ra);
+      lb.template store_plain<T, BN + PAD, false>(Bs[0], rb);
+    } else {
+      fetch(kbeg);
+      la.template store_masked<T, BM + PAD, false>(As[0], ra, pa, i0, g.M, kf, kend, g.maskA);
+      lb.template store_masked<T, BN + PAD, false>(Bs[0], rb, pb, j0, g.N, kf, kend, g.maskB);
+    }
   }
   __syncthreads();
-  for (int it = 0; it < nslab; ++it) {
-    const int cur = it & 1;
-    const bool more = it + 1 < nslab;
-    if (more) fetch(kbeg + (int64_t)(it + 1) * BK);
+  auto compute = [&](int cur) {
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       T af[SA], bf[SB];
@@ -214,6 +274,35 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
         for (int b = 0; b < SB; ++b) acc[a][b] = Tr::mma(bf[b], af[a], acc[a][b]);
     }
+  };
+  int it = 0;
+  // Next slab before s1: checked.
+  for (; it + 1 < s1 && it < nslab; ++it) {
+    const int cur = it & 1;
+    fetch(kbeg + (int64_t)(it + 1) * BK);
+    compute(cur);
+    la.template store_masked<T, BM + PAD, false>(As[cur ^ 1], ra, pa, i0, g.M, kf, kend, g.maskA);
+    lb.template store_masked<T, BN + PAD, false>(Bs[cur ^ 1], rb, pb, j0, g.N, kf, kend, g.maskB);
+    __syncthreads();
+  }
+  // Next slab in [s1, s2): plain.
+  for (; it + 1 < s2; ++it) {
+    const int cur = it & 1;
+    la.load_plain(ra);
+    lb.load_plain(rb);
+    la.advance();
+    lb.advance();
+    compute(cur);
+    la.template store_plain<T, BM + PAD, false>(As[cur ^ 1], ra);
+    lb.template store_plain<T, BN + PAD, false>(Bs[cur ^ 1], rb);
+    __syncthreads();
+  }
+  // Next slab at or after s2 (or none): checked.
+  for (; it < nslab; ++it) {
+    const int cur = it & 1;
+    const bool more = it + 1 < nslab;
+    if (more) fetch(kbeg + (int64_t)(it + 1) * BK);
+    compute(cur);
     if (more) {
       la.template store_masked<T, BM + PAD, false>(As[cur ^ 1], ra, pa, i0, g.M, kf, kend, g.maskA);
       lb.template store_masked<T, BN + PAD, false>(Bs[cur ^ 1], rb, pb, j0, g.N, kf, kend, g.maskB);
@@ -221,13 +310,14 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
     __syncthreads();
   }
 
-  // Epilogue, one 16-row slice at a time: all C values of the slice are read
-  // before any of them is written, so the loads are issued together.
-#pragma unroll
-  for (int a = 0; a < SA; ++a) {
+  // Epilogue, one 16-row slice at a time.  The C values of slice a + 1 are
+  // loaded before slice a is stored, so each slice's loads are in flight
+  // while the previous slice is written (the read latency of C is otherwise
+  // exposed once per slice).
+  double cv[SB][4];
+  auto load_c = [&](int a) {
     const int64_t i = i0 + wm * WM + 16 * a + li;
     const bool row_ok = i < g.M;
-    double cv[SB][4];
 #pragma unroll
     for (int b = 0; b < SB; ++b)
 #pragma unroll
@@ -235,15 +325,30 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
         cv[b][r] = (row_ok && j < g.N && !g.P && g.beta != 0.0) ? g.C[i + j * g.ldc] : 0.0;
       }
+  };
+  load_c(0);
+#pragma unroll
+  for (int a = 0; a < SA; ++a) {
+    const int64_t i = i0 + wm * WM + 16 * a + li;
+    const bool row_ok = i < g.M;
+    double out[SB][4];
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
+        const double v = g.alpha * (double)acc[a][b][r];
+        out[b][r] = g.P ? v : v + g.beta * cv[b][r] + ((g.add_identity && i == j) ? 1.0 : 0.0);
+      }
+    if (a + 1 < SA) load_c(a + 1);
 #pragma unroll
     for (int b = 0; b < SB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
         if (!row_ok || j >= g.N) continue;
-        const double v = g.alpha * (double)acc[a][b][r];
-        if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = v;
-        else g.C[i + j * g.ldc] = v + g.beta * cv[b][r] + ((g.add_identity && i == j) ? 1.0 : 0.0);
+        if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = out[b][r];
+        else g.C[i + j * g.ldc] = out[b][r];
       }
   }
 }
@@ -291,16 +396,26 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
     la.advance();
     lb.advance();
   };
+  // Plain slabs [s1, s2) skip the per-element selects, as in k_gemm.
+  int s1 = 0, s2 = nslab;
+  plain_slab_range<BM, BK, A_ALONG>(i0, g.M, kbeg, kend, g.maskA, &s1, &s2);
+  plain_slab_range<BN, BK, B_ALONG>(j0, g.N, kbeg, kend, g.maskB, &s1, &s2);
   if (nslab > 0) {
-    fetch(kbeg);
-    la.template store_masked<__bf16, KP, true>(As[0], ra, pa, i0, g.M, kf, kend, g.maskA);
-    lb.template store_masked<__bf16, KP, true>(Bs[0], rb, pb, j0, g.N, kf, kend, g.maskB);
+    if (s1 == 0 && s2 > 0) {
+      la.load_plain(ra);
+      lb.load_plain(rb);
+      la.advance();
+      lb.advance();
+      la.template store_plain<__bf16, KP, true>(As[0], ra);
+      lb.template store_plain<__bf16, KP, true>(Bs[0], rb);
+    } else {
+      fetch(kbeg);
+      la.template store_masked<__bf16, KP, true>(As[0], ra, pa, i0, g.M, kf, kend, g.maskA);
+      lb.template store_masked<__bf16, KP, true>(Bs[0], rb, pb, j0, g.N, kf, kend, g.maskB);
+    }
   }
   __syncthreads();
-  for (int it = 0; it < nslab; ++it) {
-    const int cur = it & 1;
-    const bool more = it + 1 < nslab;
-    if (more) fetch(kbeg + (int64_t)(it + 1) * BK);
+  auto compute = [&](int cur) {
     bf16x8 af[SA], bf[SB];
 #pragma unroll
     for (int a = 0; a < SA; ++a) af[a] = *(const bf16x8*)&As[cur][wm * WM + 16 * a + li][8 * lk];
@@ -311,17 +426,43 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 #pragma unroll
       for (int b = 0; b < SB; ++b)
         acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(bf[b], af[a], acc[a][b], 0, 0, 0);
+  };
+  int it = 0;
+  for (; it + 1 < s1 && it < nslab; ++it) {
+    const int cur = it & 1;
+    fetch(kbeg + (int64_t)(it + 1) * BK);
+    compute(cur);
+    la.template store_masked<__bf16, KP, true>(As[cur ^ 1], ra, pa, i0, g.M, kf, kend, g.maskA);
+    lb.template store_masked<__bf16, KP, true>(Bs[cur ^ 1], rb, pb, j0, g.N, kf, kend, g.maskB);
+    __syncthreads();
+  }
+  for (; it + 1 < s2; ++it) {
+    const int cur = it & 1;
+    la.load_plain(ra);
+    lb.load_plain(rb);
+    la.advance();
+    lb.advance();
+    compute(cur);
+    la.template store_plain<__bf16, KP, true>(As[cur ^ 1], ra);
+    lb.template store_plain<__bf16, KP, true>(Bs[cur ^ 1], rb);
+    __syncthreads();
+  }
+  for (; it < nslab; ++it) {
+    const int cur = it & 1;
+    const bool more = it + 1 < nslab;
+    if (more) fetch(kbeg + (int64_t)(it + 1) * BK);
+    compute(cur);
     if (more) {
       la.template store_masked<__bf16, KP, true>(As[cur ^ 1], ra, pa, i0, g.M, kf, kend, g.maskA);
       lb.template store_masked<__bf16, KP, true>(Bs[cur ^ 1], rb, pb, j0, g.N, kf, kend, g.maskB);
     }
     __syncthreads();
   }
-#pragma unroll
-  for (int a = 0; a < SA; ++a) {
+  // Epilogue as in k_gemm: slice a + 1 of C is loaded before slice a is stored.
+  double cv[SB][4];
+  auto load_c = [&](int a) {
     const int64_t i = i0 + wm * WM + 16 * a + li;
     const bool row_ok = i < g.M;
-    double cv[SB][4];
 #pragma unroll
     for (int b = 0; b < SB; ++b)
 #pragma unroll
@@ -329,15 +470,30 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
         const int64_t j = j0 + wn * WN + 16 * b + 4 * lk + r;
         cv[b][r] = (row_ok && j < g.N && !g.P && g.beta != 0.0) ? g.C[i + j * g.ldc] : 0.0;
       }
+  };
+  load_c(0);
+#pragma unroll
+  for (int a = 0; a < SA; ++a) {
+    const int64_t i = i0 + wm * WM + 16 * a + li;
+    const bool row_ok = i < g.M;
+    double out[SB][4];
+#pragma unroll
+    for (int b = 0; b < SB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t j = j0 + wn * WN + 16 * b + 4 * lk + r;
+        const double v = g.alpha * (double)acc[a][b][r];
+        out[b][r] = g.P ? v : v + g.beta * cv[b][r] + ((g.add_identity && i == j) ? 1.0 : 0.0);
+      }
+    if (a + 1 < SA) load_c(a + 1);
 #pragma unroll
     for (int b = 0; b < SB; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t j = j0 + wn * WN + 16 * b + 4 * lk + r;
         if (!row_ok || j >= g.N) continue;
-        const double v = g.alpha * (double)acc[a][b][r];
-        if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = v;
-        else g.C[i + j * g.ldc] = v + g.beta * cv[b][r] + ((g.add_identity && i == j) ? 1.0 : 0.0);
+        if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = out[b][r];
+        else g.C[i + j * g.ldc] = out[b][r];
       }
   }
 }

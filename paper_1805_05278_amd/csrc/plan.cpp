@@ -128,17 +128,30 @@ FactorLayout factor_layout(int64_t m, int64_t n, const Tuning& t, bool with_q) {
 
 // ------------------------------------------------------------ cost model
 
+const char* cost_feature_name(int f) {
+  static const char* names[F_COUNT] = {"leaf256_steps", "leaf128_steps", "tree_levels",
+                                       "tree_levels_small", "hr", "down_levels",
+                                       "gemm_launches", "gemm_weighted_flops", "panel_bytes"};
+  return (f >= 0 && f < F_COUNT) ? names[f] : "";
+}
+
 const CostCoeffs& cost_coeffs() {
-  // Fitted to factorisations measured on MI355X (the tuning sweep); see the
-  // fit record kept with the measured profiles.
+  // Fitted by least squares to factorisations timed on MI355X over a sweep of
+  // shapes and tunings, one stream, no look-ahead (the fit and its residuals
+  // are kept with the measured profiles); d0 from the GEMM depth scan.
   static const CostCoeffs c{
-      /*qr_step=*/70e-6,
-      /*qr_step128=*/38e-6,
-      /*hr=*/120e-6,
-      /*down_step=*/33e-6,
-      /*gemm_launch=*/9e-6,
-      /*gemm_rate=*/45e12,
-      /*hbm=*/5.0e12,
+      {
+          /*leaf256_steps=*/95e-6,
+          /*leaf128_steps=*/60e-6,
+          /*tree_levels=*/70e-6,
+          /*tree_levels_small=*/60e-6,
+          /*hr=*/108e-6,
+          /*down_levels=*/32e-6,
+          /*gemm_launches=*/8e-6,
+          /*gemm_weighted_flops=*/1.0 / 62e12,
+          /*panel_bytes=*/1.0 / 5.0e12,
+      },
+      /*d0=*/100.0,
       /*overlap=*/0.35,
   };
   return c;
@@ -146,95 +159,130 @@ const CostCoeffs& cost_coeffs() {
 
 namespace {
 
-struct Acc {
-  CostEstimate e;
-  double seconds = 0.0;
+struct Feat {
+  double f[F_COUNT] = {};
+  double seconds() const {
+    const CostCoeffs& c = cost_coeffs();
+    double s = 0.0;
+    for (int i = 0; i < F_COUNT; ++i) s += c.c[i] * f[i];
+    return s;
+  }
+  void add(const Feat& o) {
+    for (int i = 0; i < F_COUNT; ++i) f[i] += o.f[i];
+  }
 };
 
-double tsqr_seconds(int64_t rows, int w, int lr, int ch, int ar, bool with_q, Acc* acc) {
-  const CostCoeffs& c = cost_coeffs();
+struct Acc {
+  CostEstimate e;
+};
+
+Feat tsqr_feat(int64_t rows, int w, int lr, int ch, int ar, bool with_q) {
+  Feat r;
   const TsqrGeom g = tsqr_geometry(rows, w, lr, ch, ar);
-  const double step = g.leaf_rows == 256 ? c.qr_step : c.qr_step128;
   // Leaf: the first block of every chain in one launch (one workgroup per
   // CU at 256-row blocks, two at 128), then the stacked blocks (two per CU).
   const double slots1 = g.leaf_rows == 256 ? 256.0 : 512.0;
   const double waves1 = std::ceil((double)g.chains / slots1);
   const double waves2 = std::ceil((double)g.chains / 512.0);
-  double s = step * waves1 + (g.chain - 1) * step * waves2;
-  // Tree nodes stack (arity - 1) R factors: up to 128 rows run on the
-  // smaller node kernel.
-  const double tree_step = (g.arity - 1) * w <= 128 ? c.qr_step128 : c.qr_step;
-  s += g.levels * tree_step + c.hr + (g.levels + 1) * c.down_step;
-  const double bytes = 8.0 * (double)rows * w * (with_q ? 5.0 : 4.0);
-  s += bytes / c.hbm;
-  if (acc) {
-    acc->e.panels += 1;
-    acc->e.qr_steps += g.chain + g.levels;
-    acc->e.down_steps += g.levels + 1;
-    acc->e.panel_bytes += bytes;
-  }
-  return s;
+  r.f[g.leaf_rows == 256 ? F_LEAF256 : F_LEAF128] = waves1 + (g.chain - 1) * waves2;
+  // Tree nodes stack (arity - 1) R factors: above 128 rows they run on the
+  // blocked MFMA node kernel, up to 128 on the column-by-column one.
+  r.f[(g.arity - 1) * w > 128 ? F_TREE : F_TREE_SMALL] = g.levels;
+  r.f[F_HR] = 1.0;
+  r.f[F_DOWN] = g.levels + 1;
+  r.f[F_BYTES] = 8.0 * (double)rows * w * (with_q ? 5.0 : 4.0);
+  return r;
 }
 
-double gemm_seconds(double M, double N, double K, Acc* acc) {
-  const CostCoeffs& c = cost_coeffs();
+// The workgroups the GEMM dispatch launches for an M x N x K product (its
+// tile and split-K rule): a product with fewer than one per CU runs at that
+// share of the chip.
+double gemm_units(double M, double N, double K, bool* split) {
+  const double t128 = std::ceil(M / 128.0) * std::ceil(N / 128.0);
+  const bool big = M >= 128 && N >= 128 && (t128 >= 128 || K >= 4096);
+  const double bm = big ? 128.0 : 64.0;
+  const double tiles = std::ceil(M / bm) * std::ceil(N / bm);
+  double nsplit = 1.0;
+  const double min_chunk = K >= 1024 ? 512.0 : 32.0;
+  if (tiles < 512 && K >= 2 * min_chunk)
+    nsplit = std::max(1.0, std::min(std::floor((1024 + tiles - 1) / tiles), std::floor(K / min_chunk)));
+  *split = nsplit > 1.0;
+  return tiles * nsplit;
+}
+
+Feat gemm_feat(double M, double N, double K, Acc* acc) {
+  Feat r;
   const double fl = 2.0 * M * N * K;
-  const double by = 8.0 * (M * K + K * N + 2.0 * M * N);
-  const double tiles = std::ceil(M / 128.0) * std::ceil(N / 128.0);
-  const int launches = (tiles < 512 && K >= 64) ? 2 : 1;  // split-K reduce
-  if (acc) {
-    acc->e.gemm_launches += launches;
-    acc->e.gemm_flops += fl;
-  }
-  return std::max({c.gemm_launch * launches, fl / c.gemm_rate, by / c.hbm});
+  bool split = false;
+  const double units = gemm_units(M, N, K, &split);
+  const double d = std::max(1.0, std::min({M, N, K}));
+  r.f[F_GEMM_LAUNCH] = split ? 2.0 : 1.0;  // with the split-K reduce
+  r.f[F_GEMM_FLOP] = fl * std::max((d + cost_coeffs().d0) / d, 256.0 / std::max(units, 1.0));
+  if (acc) acc->e.gemm_flops += fl;
+  return r;
 }
 
-// Alg. 2 on a width-nk problem of mk rows: seconds, all on one stream.
-double eg_seconds(int64_t mk, int64_t nk, const Tuning& t, bool with_q, bool spine_t, bool spine,
-                  Acc* acc) {
+// Alg. 2 on a width-nk problem of mk rows, all on one stream.
+Feat eg_feat(int64_t mk, int64_t nk, const Tuning& t, bool with_q, bool spine_t, bool spine,
+             Acc* acc) {
   const int64_t n1 = eg_split(nk, t);
   if (n1 == 0) {
     int lr = t.leaf_rows, ch = t.chain, ar = t.arity;
     int a = 0, b = 0, c = 0;
     tsqr_auto(mk, (int)nk, &a, &b, &c);
-    return tsqr_seconds(mk, (int)nk, lr ? lr : a, ch ? ch : b, ar ? ar : c, with_q, acc);
+    if (acc) acc->e.panels += 1;
+    return tsqr_feat(mk, (int)nk, lr ? lr : a, ch ? ch : b, ar ? ar : c, with_q);
   }
   const int64_t n2 = nk - n1;
-  double s = eg_seconds(mk, n1, t, false, true, false, acc);
-  s += gemm_seconds(n1, n2, mk, acc) + gemm_seconds(n1, n2, n1, acc) +
-       gemm_seconds(mk, n2, n1, acc);
-  s += eg_seconds(mk - n1, n2, t, false, spine_t, spine, acc);
-  if (!spine || spine_t)
-    s += gemm_seconds(n1, n2, mk - n1, acc) + gemm_seconds(n1, n2, n2, acc) +
-         gemm_seconds(n1, n2, n1, acc);
+  Feat s = eg_feat(mk, n1, t, false, true, false, acc);
+  s.add(gemm_feat(n1, n2, mk, acc));
+  s.add(gemm_feat(n1, n2, n1, acc));
+  s.add(gemm_feat(mk, n2, n1, acc));
+  s.add(eg_feat(mk - n1, n2, t, false, spine_t, spine, acc));
+  if (!spine || spine_t) {
+    s.add(gemm_feat(n1, n2, mk - n1, acc));
+    s.add(gemm_feat(n1, n2, n2, acc));
+    s.add(gemm_feat(n1, n2, n1, acc));
+  }
   return s;
 }
 
 // Top-level update of panel (rows mk, width w) on ncols columns.
-double update_seconds(int64_t mk, int64_t w, int64_t ncols, Acc* acc) {
-  if (ncols <= 0) return 0.0;
-  return gemm_seconds(w, ncols, mk, acc) + gemm_seconds(w, ncols, w, acc) +
-         gemm_seconds(mk, ncols, w, acc);
+Feat update_feat(int64_t mk, int64_t w, int64_t ncols, Acc* acc) {
+  Feat s;
+  if (ncols <= 0) return s;
+  s.add(gemm_feat(w, ncols, mk, acc));
+  s.add(gemm_feat(w, ncols, w, acc));
+  s.add(gemm_feat(mk, ncols, w, acc));
+  return s;
 }
 
 }  // namespace
 
 static CostEstimate predict_impl(int64_t m, int64_t n, const Tuning& t, bool lstsq) {
   Acc acc;
+  Feat tot;
   double s = 0.0;
   if (t.t_layout != T_BLOCKED) {
-    s = eg_seconds(m, n, t, false, !lstsq, true, &acc);
+    tot = eg_feat(m, n, t, false, !lstsq, true, &acc);
+    s = tot.seconds();
     acc.e.critical_s = s;
   } else {
     const int64_t nb = top_panel(t, n);
-    const CostCoeffs& c = cost_coeffs();
     std::vector<double> F, Un, Ur;
     for (int64_t j = 0; j < n; j += nb) {
       const int64_t w = std::min(nb, n - j);
-      F.push_back(eg_seconds(m - j, w, t, false, true, false, &acc));
+      const Feat fp = eg_feat(m - j, w, t, false, true, false, &acc);
       const int64_t nxt = std::min(nb, std::max<int64_t>(n - j - w, 0));
-      Un.push_back(update_seconds(m - j, w, nxt, &acc));
-      Ur.push_back(update_seconds(m - j, w, n - j - w - nxt, &acc));
+      const Feat un = update_feat(m - j, w, nxt, &acc);
+      const Feat ur = update_feat(m - j, w, n - j - w - nxt, &acc);
+      F.push_back(fp.seconds());
+      Un.push_back(un.seconds());
+      Ur.push_back(ur.seconds());
+      acc.e.schedule.push_back({fp.f, un.f, ur.f});
+      tot.add(fp);
+      tot.add(un);
+      tot.add(ur);
     }
     double crit = 0.0, upd = 0.0;
     for (double f : F) crit += f;
@@ -242,15 +290,17 @@ static CostEstimate predict_impl(int64_t m, int64_t n, const Tuning& t, bool lst
     acc.e.critical_s = crit;
     acc.e.update_s = upd;
     if (t.lookahead) {
+      const double ov = cost_coeffs().overlap;
       s = F[0];
       for (size_t k = 0; k + 1 < F.size(); ++k) {
         const double a = Un[k] + F[k + 1], b = Ur[k];
-        s += std::max(a, b) + c.overlap * std::min(a, b);
+        s += std::max(a, b) + ov * std::min(a, b);
       }
     } else {
-      for (size_t k = 0; k < F.size(); ++k) s += F[k] + Un[k] + Ur[k];
+      s = tot.seconds();
     }
   }
+  for (int i = 0; i < F_COUNT; ++i) acc.e.f[i] = tot.f[i];
   acc.e.seconds = s;
   return acc.e;
 }
@@ -281,7 +331,7 @@ void tsqr_auto(int64_t rows, int w, int* leaf_rows, int* chain, int* arity) {
       if (ch > 1 && ch > P0) continue;
       for (int ar : {2, 3, 5}) {
         if (ar > max_arity) continue;
-        const double s = tsqr_seconds(rows, w, lr, ch, ar, false, nullptr);
+        const double s = tsqr_feat(rows, w, lr, ch, ar, false).seconds();
         if (s < best * (1.0 - 1e-9)) {
           best = s;
           bl = lr;
@@ -378,18 +428,46 @@ std::string describe_plan(int64_t m, int64_t n, const Tuning& t) {
   std::snprintf(buf, sizeof buf,
                 "{\"m\":%lld,\"n\":%lld,\"tuning\":{\"b\":%lld,\"bstar\":%d,\"nb\":%lld,"
                 "\"leaf_rows\":%d,\"chain\":%d,\"arity\":%d,\"t_layout\":%d,\"lookahead\":%d},"
-                "\"cost\":{\"seconds\":%.9g,\"panels\":%lld,\"qr_steps\":%lld,\"down_steps\":%lld,"
-                "\"gemm_launches\":%lld,\"gemm_flops\":%.9g,\"panel_bytes\":%.9g,"
+                "\"cost\":{\"seconds\":%.9g,\"panels\":%lld,\"gemm_flops\":%.9g,"
                 "\"critical_s\":%.9g,\"update_s\":%.9g},"
                 "\"layout\":{\"tsqr\":%lld,\"wa\":%lld,\"wb\":%lld,\"scratch\":%lld,\"u1\":%lld,"
                 "\"u2\":%lld,\"ua1\":%lld,\"ua2\":%lld,\"scratch_aux\":%lld,\"total\":%lld},",
                 (long long)m, (long long)n, (long long)t.b, t.bstar, (long long)t.nb, t.leaf_rows,
                 t.chain, t.arity, t.t_layout, t.lookahead, e.seconds, (long long)e.panels,
-                (long long)e.qr_steps, (long long)e.down_steps, (long long)e.gemm_launches,
-                e.gemm_flops, e.panel_bytes, e.critical_s, e.update_s, (long long)L.tsqr,
+                e.gemm_flops, e.critical_s, e.update_s, (long long)L.tsqr,
                 (long long)L.wa, (long long)L.wb, (long long)L.scratch, (long long)L.u1,
                 (long long)L.u2, (long long)L.ua1, (long long)L.ua2, (long long)L.scratch_aux,
                 (long long)L.total);
+  s += buf;
+  // The cost model's features (one-stream counts) and coefficients.
+  s += "\"features\":{";
+  for (int i = 0; i < F_COUNT; ++i) {
+    std::snprintf(buf, sizeof buf, "%s\"%s\":%.9g", i ? "," : "", cost_feature_name(i), e.f[i]);
+    s += buf;
+  }
+  s += "},\"schedule\":[";
+  // BLOCKED: per top-level panel, the features of its factorisation, of the
+  // update of the next panel's columns and of the rest of the update.
+  for (size_t k = 0; k < e.schedule.size(); ++k) {
+    s += k ? ",[" : "[";
+    for (int part = 0; part < 3; ++part) {
+      s += part ? ",[" : "[";
+      for (int i = 0; i < F_COUNT; ++i) {
+        std::snprintf(buf, sizeof buf, "%s%.9g", i ? "," : "", e.schedule[k].part[part][i]);
+        s += buf;
+      }
+      s += "]";
+    }
+    s += "]";
+  }
+  s += "],\"coefficients\":{";
+  for (int i = 0; i < F_COUNT; ++i) {
+    std::snprintf(buf, sizeof buf, "%s\"%s\":%.9g", i ? "," : "", cost_feature_name(i),
+                  cost_coeffs().c[i]);
+    s += buf;
+  }
+  std::snprintf(buf, sizeof buf, ",\"d0\":%.9g,\"overlap\":%.9g},", cost_coeffs().d0,
+                cost_coeffs().overlap);
   s += buf;
   // Recursion nodes [c0, rows, width, n1] (n1 = 0: base-case TSQR panel) of
   // every top-level panel.

@@ -67,31 +67,59 @@ struct FactorLayout {
 // with_q: room for forming the explicit thin Q after the factorisation.
 FactorLayout factor_layout(int64_t m, int64_t n, const Tuning& t, bool with_q = false);
 
-// Cost-model coefficients (seconds, bytes per second, flops per second),
-// fitted to measured factorisations on MI355X.
+// The cost model is linear in its coefficients: a factorisation's time on one
+// stream is sum_i coef_i * feature_i over these counts (the paper's
+// alpha S + beta W + gamma F of Sec. 3, with S split by the kind of launch,
+// since each kind has its own latency on one GPU).
+enum CostFeature : int {
+  F_LEAF256 = 0,  // serial block-QR steps of 256-row leaves (per launch wave)
+  F_LEAF128,      // the same at 128-row leaves
+  F_TREE,         // tree levels on the blocked node kernel (> 128 stacked rows)
+  F_TREE_SMALL,   // tree levels on the column-by-column node kernel
+  F_HR,           // Householder reconstructions (one per TSQR panel)
+  F_DOWN,         // downsweep levels (tree levels + the leaf level)
+  F_GEMM_LAUNCH,  // GEMM and split-K reduce launches
+  F_GEMM_FLOP,    // GEMM flops weighted by (d + d0) / d, d the smallest dimension
+  F_BYTES,        // algorithmic HBM bytes of the TSQR kernels
+  F_COUNT
+};
+const char* cost_feature_name(int f);
+
+// Coefficients (seconds per count; F_GEMM_FLOP: seconds per weighted flop,
+// the inverse of the asymptotic FP64 MFMA rate; F_BYTES: the inverse of the
+// panel kernels' bandwidth), the GEMM depth d0 at which a product runs at
+// half its asymptotic rate, and the look-ahead overlap: the share of the
+// shorter of the two concurrent streams that still adds to the time.
 struct CostCoeffs {
-  double qr_step;      // one serial block QR of a chain or tree node (256-row blocks)
-  double qr_step128;   // the same at 128-row blocks
-  double hr;           // Householder reconstruction at the root
-  double down_step;    // one downsweep level
-  double gemm_launch;  // floor of one GEMM (or split-K reduce) launch
-  double gemm_rate;    // sustained FP64 MFMA rate of the update GEMMs
-  double hbm;          // sustained HBM bandwidth of the panel kernels
-  double overlap;      // look-ahead: share of the shorter stream that still adds
+  double c[F_COUNT];
+  double d0;
+  double overlap;
 };
 const CostCoeffs& cost_coeffs();
+
+// Features of one top-level panel of a BLOCKED factorisation: its own
+// factorisation, the update of the next panel's columns, the rest of the
+// update.
+struct PanelFeatures {
+  double part[3][F_COUNT];
+  PanelFeatures(const double* a, const double* b, const double* c) {
+    for (int i = 0; i < F_COUNT; ++i) {
+      part[0][i] = a[i];
+      part[1][i] = b[i];
+      part[2][i] = c[i];
+    }
+  }
+};
 
 // What the cost model counts for one factorisation.
 struct CostEstimate {
   double seconds = 0.0;
+  double f[F_COUNT] = {};    // features summed over the whole factorisation
   int64_t panels = 0;        // TSQR panels
-  int64_t qr_steps = 0;      // serial block-QR steps on the critical path
-  int64_t down_steps = 0;    // downsweep levels
-  int64_t gemm_launches = 0;
   double gemm_flops = 0.0;   // algorithmic flops of the GEMMs
-  double panel_bytes = 0.0;  // algorithmic HBM bytes of the TSQR kernels
-  double critical_s = 0.0;   // panel chain alone
+  double critical_s = 0.0;   // panel factorisations alone
   double update_s = 0.0;     // top-level updates alone (BLOCKED)
+  std::vector<PanelFeatures> schedule;  // BLOCKED: per top-level panel
 };
 CostEstimate predict(int64_t m, int64_t n, const Tuning& t);
 
