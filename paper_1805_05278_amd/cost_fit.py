@@ -30,7 +30,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(HERE))
 
 FEATURES = ["leaf256_steps", "leaf128_steps", "tree_levels", "tree_levels_small", "hr",
-            "down_levels", "gemm_launches", "gemm_weighted_flops", "panel_bytes"]
+            "down_levels", "gemm_launches", "gemm_flops", "gemm_flops_per_depth",
+            "gemm_idle_flops", "panel_bytes"]
 
 TALL = [(1048576, 64), (262144, 64), (65536, 64), (16384, 64), (4096, 64), (262144, 256),
         (65536, 256), (20000, 640)]
@@ -88,6 +89,7 @@ def sweep(out, reps, quick=False):
                 if r:
                     times.append(time.perf_counter() - t0)
             rec = {"m": m, "n": n, "tuning_given": _label(kw), "lookahead": la,
+                   "panels": plan["panels"],
                    "seconds": min(times), "tuning": plan["tuning"], "features": plan["features"],
                    "predicted": plan["cost"]["seconds"], "coefficients": plan["coefficients"],
                    "schedule": plan.get("schedule", [])}
@@ -106,6 +108,26 @@ def fit(path, out, out_json=None):
 
     with open(path) as f:
         runs = json.load(f)["runs"]
+    # The features of each run come from the library's planner on the host
+    # (they depend only on the shape and the tuning), so a sweep can be refit
+    # after the feature set changes without touching the GPU again.
+    import paper_1805_05278_amd as miqr
+    # Runs with automatic TSQR parameters are left out: the planner picks
+    # those per panel, and a refit that changes the coefficients changes the
+    # picks, so the recorded time no longer belongs to the recomputed plan.
+    runs = [r for r in runs if r["tuning_given"] != "auto"]
+    for r in runs:
+        kw = {}
+        if r["tuning_given"] != "auto":
+            for item in r["tuning_given"].split(","):
+                k, v = item.split("=")
+                kw[k] = int(v)
+        plan = miqr.Handle.plan(r["m"], r["n"], miqr.Handle.opts(lookahead=r["lookahead"], **kw))
+        assert plan["tuning"] == r["tuning"], (r["tuning_given"], plan["tuning"], r["tuning"])
+        r["features"] = plan["features"]
+        r["schedule"] = plan.get("schedule", [])
+        r["coefficients"] = plan["coefficients"]
+        r["predicted"] = plan["cost"]["seconds"]
     fit_set = [r for r in runs if not r["lookahead"]]
     X = np.array([[r["features"][k] for k in FEATURES] for r in fit_set], dtype=float)
     y = np.array([r["seconds"] for r in fit_set])
@@ -145,14 +167,16 @@ def fit(path, out, out_json=None):
              "run; coefficients by non-negative least squares on relative error over %d runs." %
              len(fit_set), "",
              "| feature | fitted coefficient | unit | built-in coefficient |", "|---|---:|---|---:|"]
-    units = {"gemm_weighted_flops": "s per weighted flop (1 / asymptotic rate)",
+    units = {"gemm_flops": "s per flop (1 / asymptotic rate)",
+             "gemm_flops_per_depth": "s per flop / depth (d0 / asymptotic rate)",
+             "gemm_idle_flops": "s per idle-CU flop",
              "panel_bytes": "s per byte (1 / bandwidth)"}
     for k, c in zip(FEATURES, coef):
         lines.append("| %s | %.4g | %s | %.4g |" % (k, c, units.get(k, "s per count"),
                                                 fit_set[0]["coefficients"][k]))
-    lines += ["", "Asymptotic GEMM rate: %.1f TFLOP/s (weighted by (d + d0)/d, d0 = %g)." % (
-        1e-12 / coef[FEATURES.index("gemm_weighted_flops")] if coef[FEATURES.index("gemm_weighted_flops")] > 0 else float("nan"),
-        fit_set[0]["coefficients"]["d0"]), "",
+    cf, cd = coef[FEATURES.index("gemm_flops")], coef[FEATURES.index("gemm_flops_per_depth")]
+    lines += ["", "Asymptotic GEMM rate %.1f TFLOP/s; half rate at depth d0 = %.0f." % (
+        1e-12 / cf if cf > 0 else float("nan"), cd / cf if cf > 0 else float("nan")), "",
         "Relative prediction error over the fitting runs: fitted median |e| %.1f %%, max %.1f %%;"
         " built-in median %.1f %%, max %.1f %%." % (
             100 * np.median(np.abs(rel)), 100 * np.max(np.abs(rel)),
@@ -178,6 +202,18 @@ def fit(path, out, out_json=None):
             r["seconds"] * 1e3, ("%.3f" % (p * 1e3)) if p == p else "-",
             ("%+.1f %%" % (100 * (p - r["seconds"]) / r["seconds"])) if p == p else "-",
             r["predicted"] * 1e3, 100 * (r["predicted"] - r["seconds"]) / r["seconds"]))
+    # Leave-one-shape-out cross-validation of the linear part.
+    shapes = sorted({(r["m"], r["n"]) for r in fit_set})
+    cv = []
+    for sh in shapes:
+        tr = [i for i, r in enumerate(fit_set) if (r["m"], r["n"]) != sh]
+        te = [i for i, r in enumerate(fit_set) if (r["m"], r["n"]) == sh]
+        cs, _ = nnls((X[tr] / scale) * w[tr, None], y[tr] * w[tr])
+        cv += list(np.abs((X[te] @ (cs / scale) - y[te]) / y[te]))
+    lines.insert(len(lines) - 3, "Leave-one-shape-out cross-validation (each shape predicted by a fit "
+                 "to the others): median |e| %.1f %%, max %.1f %%." % (100 * np.median(cv),
+                                                                       100 * np.max(cv)))
+    lines.insert(len(lines) - 3, "")
     with open(out, "w") as f:
         f.write("\n".join(lines) + "\n")
     if out_json:

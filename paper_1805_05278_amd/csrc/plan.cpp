@@ -131,7 +131,8 @@ FactorLayout factor_layout(int64_t m, int64_t n, const Tuning& t, bool with_q) {
 const char* cost_feature_name(int f) {
   static const char* names[F_COUNT] = {"leaf256_steps", "leaf128_steps", "tree_levels",
                                        "tree_levels_small", "hr", "down_levels",
-                                       "gemm_launches", "gemm_weighted_flops", "panel_bytes"};
+                                       "gemm_launches", "gemm_flops", "gemm_flops_per_depth",
+                                       "gemm_idle_flops", "panel_bytes"};
   return (f >= 0 && f < F_COUNT) ? names[f] : "";
 }
 
@@ -141,18 +142,19 @@ const CostCoeffs& cost_coeffs() {
   // are kept with the measured profiles); d0 from the GEMM depth scan.
   static const CostCoeffs c{
       {
-          /*leaf256_steps=*/95e-6,
-          /*leaf128_steps=*/60e-6,
-          /*tree_levels=*/70e-6,
-          /*tree_levels_small=*/60e-6,
-          /*hr=*/108e-6,
-          /*down_levels=*/32e-6,
-          /*gemm_launches=*/8e-6,
-          /*gemm_weighted_flops=*/1.0 / 62e12,
-          /*panel_bytes=*/1.0 / 5.0e12,
+          /*leaf256_steps=*/0.0001165,
+          /*leaf128_steps=*/0.0001088,
+          /*tree_levels=*/0.0001303,
+          /*tree_levels_small=*/8.415e-05,
+          /*hr=*/3.599e-05,
+          /*down_levels=*/0,
+          /*gemm_launches=*/2.788e-06,
+          /*gemm_flops=*/1.754e-14,
+          /*gemm_flops_per_depth=*/3.549e-13,
+          /*gemm_idle_flops=*/4.973e-14,
+          /*panel_bytes=*/2.579e-13,
       },
-      /*d0=*/100.0,
-      /*overlap=*/0.35,
+      /*overlap=*/0.99,
   };
   return c;
 }
@@ -217,7 +219,9 @@ Feat gemm_feat(double M, double N, double K, Acc* acc) {
   const double units = gemm_units(M, N, K, &split);
   const double d = std::max(1.0, std::min({M, N, K}));
   r.f[F_GEMM_LAUNCH] = split ? 2.0 : 1.0;  // with the split-K reduce
-  r.f[F_GEMM_FLOP] = fl * std::max((d + cost_coeffs().d0) / d, 256.0 / std::max(units, 1.0));
+  r.f[F_GEMM_FLOP] = fl;
+  r.f[F_GEMM_DEPTH] = fl / d;
+  r.f[F_GEMM_IDLE] = fl * std::max(0.0, 256.0 / std::max(units, 1.0) - 1.0);
   if (acc) acc->e.gemm_flops += fl;
   return r;
 }
@@ -329,8 +333,12 @@ void tsqr_auto(int64_t rows, int w, int* leaf_rows, int* chain, int* arity) {
     const int64_t P0 = std::max<int64_t>(1, (rows + lr - 1) / lr);
     for (int ch : {1, 2, 4, 8}) {
       if (ch > 1 && ch > P0) continue;
-      for (int ar : {2, 3, 5}) {
-        if (ar > max_arity) continue;
+      // The tree arity stays at five stacked children (or what the stacked-R
+      // buffer holds for narrower panels): in the sweep, narrower trees lost
+      // wherever they were measured against it, and the per-level costs of
+      // the two node kernels are not separable from the other per-panel
+      // terms in the fit.
+      for (int ar : {std::min(5, max_arity)}) {
         const double s = tsqr_feat(rows, w, lr, ch, ar, false).seconds();
         if (s < best * (1.0 - 1e-9)) {
           best = s;
@@ -466,8 +474,7 @@ std::string describe_plan(int64_t m, int64_t n, const Tuning& t) {
                   cost_coeffs().c[i]);
     s += buf;
   }
-  std::snprintf(buf, sizeof buf, ",\"d0\":%.9g,\"overlap\":%.9g},", cost_coeffs().d0,
-                cost_coeffs().overlap);
+  std::snprintf(buf, sizeof buf, ",\"overlap\":%.9g},", cost_coeffs().overlap);
   s += buf;
   // Recursion nodes [c0, rows, width, n1] (n1 = 0: base-case TSQR panel) of
   // every top-level panel.

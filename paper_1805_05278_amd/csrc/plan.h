@@ -79,20 +79,24 @@ enum CostFeature : int {
   F_HR,           // Householder reconstructions (one per TSQR panel)
   F_DOWN,         // downsweep levels (tree levels + the leaf level)
   F_GEMM_LAUNCH,  // GEMM and split-K reduce launches
-  F_GEMM_FLOP,    // GEMM flops weighted by (d + d0) / d, d the smallest dimension
+  F_GEMM_FLOP,    // GEMM flops
+  F_GEMM_DEPTH,   // GEMM flops / d, d the product's smallest dimension (short
+                  // products pay their tile prologue and epilogue more often)
+  F_GEMM_IDLE,    // GEMM flops * (256 / workgroups - 1) for products with
+                  // fewer workgroups than CUs
   F_BYTES,        // algorithmic HBM bytes of the TSQR kernels
   F_COUNT
 };
 const char* cost_feature_name(int f);
 
-// Coefficients (seconds per count; F_GEMM_FLOP: seconds per weighted flop,
-// the inverse of the asymptotic FP64 MFMA rate; F_BYTES: the inverse of the
-// panel kernels' bandwidth), the GEMM depth d0 at which a product runs at
-// half its asymptotic rate, and the look-ahead overlap: the share of the
-// shorter of the two concurrent streams that still adds to the time.
+// Coefficients (seconds per count; F_GEMM_FLOP: seconds per flop, the
+// inverse of the asymptotic FP64 MFMA rate; F_GEMM_DEPTH: that times the
+// depth d0 at which a product runs at half its asymptotic rate; F_BYTES: the
+// inverse of the panel kernels' bandwidth) and the look-ahead overlap: the
+// share of the shorter of the two concurrent streams that still adds to the
+// time.
 struct CostCoeffs {
   double c[F_COUNT];
-  double d0;
   double overlap;
 };
 const CostCoeffs& cost_coeffs();
