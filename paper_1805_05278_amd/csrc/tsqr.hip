@@ -1075,78 +1075,102 @@ __device__ __forceinline__ void hr_mm(double (*C)[kNB + 1], double (*A)[kNB + 1]
     for (int r = 0; r < 4; ++r) C[16 * w + lk + 4 * r][16 * ct + li] = acc[ct][r];
 }
 
-// One step j of the sign-modified LU (thread (i, p) holds X[i][p + 4m] in
-// xr[m] and L^{-1}[i][p + 4m] in er[m]); recurses over j so that the register
-// slot of column j, j / 4, is a constant.
-template <int J>
-__device__ __forceinline__ void hr_lu(double (&xr)[16], double (&er)[16], int i, int p, int nbr,
-                                      double (*Rb)[2][4][16], double* Sv, double* Ui) {
-  if constexpr (J < kNB) {
-    if (J < nbr) {
-      constexpr int slot = J & 1, q = J & 3, mj = J >> 2;
-      if (i == J) {
-        if (p == q) {
-          const double sg = (xr[mj] >= 0.0) ? 1.0 : -1.0;
-          xr[mj] += sg;
-          Sv[J] = sg;
-          Ui[J] = 1.0 / xr[mj];
-        }
-#pragma unroll
-        for (int m = 0; m < 16; m += 2) {
-          *(double2*)&Rb[slot][0][p][m] = make_double2(xr[m], xr[m + 1]);
-          *(double2*)&Rb[slot][1][p][m] = make_double2(er[m], er[m + 1]);
-        }
-      }
-      __syncthreads();
-      if (i > J && i < nbr) {
-        // Multiplier l = X[i][J] / U_JJ, formed by the thread holding column
-        // J and shared with the other three threads of the row.
-        double l = (p == q) ? xr[mj] * Ui[J] : 0.0;
-        l = dpp_mov<q | (q << 2) | (q << 4) | (q << 6)>(l);
-        if (p == q) xr[mj] = l;
-#pragma unroll
-        for (int m = 0; m < 16; m += 2) {
-          const double2 rx = *(const double2*)&Rb[slot][0][p][m];
-          const double2 re = *(const double2*)&Rb[slot][1][p][m];
-          const int k0 = p + 4 * m, k1 = k0 + 4;
-          xr[m] -= (k0 > J ? l : 0.0) * rx.x;
-          xr[m + 1] -= (k1 > J ? l : 0.0) * rx.y;
-          er[m] -= (k0 <= J ? l : 0.0) * re.x;
-          er[m + 1] -= (k1 <= J ? l : 0.0) * re.y;
-        }
-      }
-    }
-    hr_lu<J + 1>(xr, er, i, p, nbr, Rb, Sv, Ui);
+// Every lane of a quad receives lane q's value (quad_perm [q, q, q, q]); q is
+// a constant after unrolling.
+__device__ __forceinline__ double quad_bcast(double v, int q) {
+  switch (q) {
+    case 0: return dpp_mov<0x00>(v);
+    case 1: return dpp_mov<0x55>(v);
+    case 2: return dpp_mov<0xAA>(v);
+    default: return dpp_mov<0xFF>(v);
   }
 }
 
-// Backward elimination for U^{-1}, step J (descending): rows above J lose
-// U[i][J] / U_JJ times row J of the running inverse (mr).
-template <int J>
-__device__ __forceinline__ void hr_uinv(const double (&xr)[16], double (&mr)[16], int i, int p,
-                                        int nbr, double (*Rb)[2][4][16], const double* Ui) {
-  if constexpr (J >= 1) {
-    if (J < nbr) {
-      constexpr int slot = J & 1, q = J & 3, mj = J >> 2;
-      if (i == J) {
+// Sign-modified LU without pivoting (App. C.2) of the 64 x 64 X whose rows
+// sit in registers: thread (i, p) holds row i's columns p + 4 (s + m) in
+// xr[s] during outer step m, and row i of the running L^{-1} (columns p + 4 s)
+// in er[s].  Step J = 4 m + q: before eliminating column J, S_JJ = sgn(X^_JJ)
+// (+1 for >= 0) and X^_JJ += S_JJ; the pivot row goes to Rb (double-buffered
+// by step parity) and every lower row subtracts its multiple.  After the four
+// steps of an outer step, column 4 m + p is final in every row: it is stored
+// to Xm and the registers shift down one slot, so the pivot column is always
+// slot 0 and no register index depends on the step (a loop of 16 outer steps
+// instead of 64 unrolled ones).  Row J of L^{-1} is zero right of column J,
+// so its update needs no mask.
+__device__ __forceinline__ void hr_lu(double (&xr)[16], double (&er)[16], int i, int p, int nbr,
+                                      double (*Rb)[2][4][16], double* Sv, double* Ui,
+                                      double (*Xm)[kNB + 1]) {
+  for (int m = 0; m < 16; ++m) {
 #pragma unroll
-        for (int m = 0; m < 16; m += 2)
-          *(double2*)&Rb[slot][0][p][m] = make_double2(mr[m], mr[m + 1]);
-      }
-      __syncthreads();
-      if (i < J) {
-        double f = (p == q) ? xr[mj] * Ui[J] : 0.0;
-        f = dpp_mov<q | (q << 2) | (q << 4) | (q << 6)>(f);
+    for (int q = 0; q < 4; ++q) {
+      const int J = 4 * m + q;
+      if (J < nbr) {
+        const int slot = q & 1;
+        if (i == J) {
+          if (p == q) {
+            const double sg = (xr[0] >= 0.0) ? 1.0 : -1.0;
+            xr[0] += sg;
+            Sv[J] = sg;
+            Ui[J] = 1.0 / xr[0];
+          }
 #pragma unroll
-        for (int m = 0; m < 16; m += 2) {
-          const double2 rm = *(const double2*)&Rb[slot][0][p][m];
-          const int k0 = p + 4 * m, k1 = k0 + 4;
-          mr[m] -= (k0 >= J ? f : 0.0) * rm.x;
-          mr[m + 1] -= (k1 >= J ? f : 0.0) * rm.y;
+          for (int t = 0; t < 16; t += 2) {
+            *(double2*)&Rb[slot][0][p][t] = make_double2(xr[t], xr[t + 1]);
+            *(double2*)&Rb[slot][1][p][t] = make_double2(er[t], er[t + 1]);
+          }
+        }
+        __syncthreads();
+        if (i > J && i < nbr) {
+          // Multiplier l = X[i][J] / U_JJ, formed by the thread holding
+          // column J and shared with the other three threads of the row.
+          double l = (p == q) ? xr[0] * Ui[J] : 0.0;
+          l = quad_bcast(l, q);
+          if (p == q) xr[0] = l;
+#pragma unroll
+          for (int t = 0; t < 16; t += 2) {
+            const double2 rx = *(const double2*)&Rb[slot][0][p][t];
+            const double2 re = *(const double2*)&Rb[slot][1][p][t];
+            // slot 0 holds column 4 m + p: updated only right of the pivot
+            xr[t] -= ((t > 0 || p > q) ? l : 0.0) * rx.x;
+            xr[t + 1] -= l * rx.y;
+            er[t] -= l * re.x;
+            er[t + 1] -= l * re.y;
+          }
         }
       }
     }
-    hr_uinv<J - 1>(xr, mr, i, p, nbr, Rb, Ui);
+    Xm[i][4 * m + p] = xr[0];
+#pragma unroll
+    for (int t = 0; t < 15; ++t) xr[t] = xr[t + 1];
+    xr[15] = 0.0;
+  }
+}
+
+// U^{-1} by backward elimination (U in the upper triangle of Xm): for J
+// descending, rows above J lose U[i][J] / U_JJ times row J of the running
+// inverse mr (thread (i, p): columns p + 4 s).  Row J of the running inverse
+// is zero left of column J, so the update needs no mask; the rows are scaled
+// by 1 / U_ii afterwards.
+__device__ __forceinline__ void hr_uinv(double (&mr)[16], int i, int p, int nbr,
+                                        double (*Rb)[2][4][16], const double* Ui,
+                                        double (*Xm)[kNB + 1]) {
+  for (int J = nbr - 1; J >= 1; --J) {
+    const int slot = J & 1;
+    if (i == J) {
+#pragma unroll
+      for (int t = 0; t < 16; t += 2)
+        *(double2*)&Rb[slot][0][p][t] = make_double2(mr[t], mr[t + 1]);
+    }
+    __syncthreads();
+    if (i < J) {
+      const double f = Xm[i][J] * Ui[J];
+#pragma unroll
+      for (int t = 0; t < 16; t += 2) {
+        const double2 rm = *(const double2*)&Rb[slot][0][p][t];
+        mr[t] -= f * rm.x;
+        mr[t + 1] -= f * rm.y;
+      }
+    }
   }
 }
 
@@ -1240,8 +1264,7 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
   // S_jj = sgn(X^_jj) (+1 for >= 0) and X^_jj += S_jj.  The row operations are
   // applied to the identity alongside, which therefore ends as L^{-1}; then
   // U^{-1} by backward elimination.  Thread (i, p) keeps row i's columns
-  // p, p + 4, ... in registers; hr_lu_step / hr_uinv_step are unrolled over
-  // the step index so that every register index is a constant.
+  // p, p + 4, ... in registers (hr_lu, hr_uinv).
   {
     const int i = t >> 2, p = t & 3;
     double xr[16], er[16], mr[16];
@@ -1253,14 +1276,13 @@ __global__ __launch_bounds__(256) void k_tsqr_hr(HRArgs a) {
       mr[m] = (i == k) ? 1.0 : 0.0;
     }
     __syncthreads();
-    hr_lu<0>(xr, er, i, p, nbr, Rb, Sv, Ui);
-    hr_uinv<63>(xr, mr, i, p, nbr, Rb, Ui);
-    // Back to LDS for the products below: X (L below, U on and above the
-    // diagonal), L^{-1} in Bm, U^{-1} (rows scaled by 1/U_ii) in Mm.
+    hr_lu(xr, er, i, p, nbr, Rb, Sv, Ui, Xm);  // X (L below, U on and above) to Xm
+    __syncthreads();
+    hr_uinv(mr, i, p, nbr, Rb, Ui, Xm);
+    // L^{-1} in Bm, U^{-1} (rows scaled by 1/U_ii) in Mm.
 #pragma unroll
     for (int m = 0; m < 16; ++m) {
       const int k = p + 4 * m;
-      Xm[i][k] = xr[m];
       Bm[i][k] = er[m];
       Mm[i][k] = (i < nbr) ? mr[m] * Ui[i] : mr[m];
     }
