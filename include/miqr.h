@@ -285,26 +285,47 @@ typedef struct qr_batch_item {
     int64_t ldb;
 } qr_batch_item;
 
-/* Many independent least-squares problems in one persistent launch.  Each
+/* Many independent least-squares problems in persistent launches.  Each
  * problem is solved by one workgroup: Householder QR of the augmented matrix
  * [A | B] by a flat TSQR sweep over 64-row blocks (the TSQR of Sec. 5 /
- * App. C.1 with a chain as its reduction tree; dlarfg sign rule), which leaves
- * R and the top n rows of Q^T B, then back substitution.  Workgroups pop
- * problems from a device queue, largest first.  A problem's arithmetic does
- * not depend on the other problems in the call, so its result is bitwise the
- * same alone and in any batch.
+ * App. C.1 with a chain as its reduction tree; dlarfg sign rule), the block's
+ * reflectors applied sixteen at a time in the compact WY form of Sec. 2.3 on
+ * MFMA, which leaves R and the top n rows of Q^T B, then back substitution.
+ * Workgroups pop problems from device queues (one per register budget, by
+ * n + nrhs), largest first.  A problem's arithmetic does not depend on the
+ * other problems in the call, so its result is bitwise the same alone and in
+ * any batch.
  *   items (host array of `count`): problems; pointers must not overlap.
- *   opts: NULL or precision MIQR_FP64 (the sweep has no GEMM for a lower
- *   precision to speed up: MIQR_ENOTSUP otherwise).
+ *   opts: NULL or precision MIQR_FP64, MIQR_MIXED_FP32 or MIQR_MIXED_BF16
+ *   (other fields ignored; normalize and Q must be unset).  Mixed: the sweep
+ *   runs on an FP32 working copy of each block with the two large products of
+ *   every panel update on FP32 or BF16 MFMA (FP32 accumulation); reflector
+ *   generation, T and R stay in FP64.  Each solution is then refined in FP64
+ *   against the original A and B (R-preconditioned conjugate gradients on the
+ *   normal equations, residual recomputed from A each iteration) until every
+ *   right-hand side's backward error (qr_backward_error's measure) is
+ *   <= 1e-13 (the kernel aims at 5e-14, a margin for the rounding of its own
+ *   estimate); a problem that does not get there within 40 iterations, or
+ *   stops halving its error over four, is solved again in FP64.  Mixed
+ *   precisions synchronise the stream.
  *   status (host, `count` int32, may be NULL): when given, the call
  *   synchronises the stream and writes 0, or j + 1 when R_jj == 0 exactly
  *   (that problem's B then holds the top n rows of Q^T B and A is unchanged).
  * Returns MIQR_ESINGULAR if status was given and some problem is singular.
- * Errors: MIQR_EINVAL (a bad item; nothing is enqueued), MIQR_ENOMEM,
- * MIQR_EHIP, MIQR_ENOTSUP. */
+ * Errors: MIQR_EINVAL (a bad item or precision; nothing is enqueued),
+ * MIQR_ENOMEM, MIQR_EHIP, MIQR_ENOTSUP. */
 miqr_status qr_lstsq_batched(miqr_handle handle, void *stream, int64_t count,
                              const qr_batch_item *items, const qr_opts *opts,
                              int32_t *status);
+
+/* qr_lstsq_batched with, per item, the refinement iterations of a mixed
+ * precision: iters (host, `count` int32, may be NULL) receives 0 for FP64,
+ * the FP64 refinement iterations that met the target, or -1 for a problem
+ * solved again in FP64.  Synchronises the stream when status or iters is
+ * given. */
+miqr_status qr_lstsq_batched_ex(miqr_handle handle, void *stream, int64_t count,
+                                const qr_batch_item *items, const qr_opts *opts,
+                                int32_t *status, int32_t *iters);
 
 /* ---- Serving loop -------------------------------------------------------
  * A least-squares server on one device.  Requests (host matrices) wait in
@@ -327,8 +348,12 @@ typedef struct qr_server_opts {
                              (0: 2^20) */
     int64_t stage_bytes;  /* per in-flight batch, solution staging (0: 64 MiB) */
     int32_t keep_factors; /* nonzero: each factorisation stays on the device
-                             for qr_server_resolve until qr_server_release */
-    int32_t pad;
+                             for qr_server_resolve until qr_server_release
+                             (FP64 only) */
+    int32_t precision;    /* MIQR_FP64 (0), MIQR_MIXED_FP32 or MIQR_MIXED_BF16:
+                             as for qr_lstsq_batched; a request whose
+                             refinement misses 1e-13 is solved again in FP64
+                             in a later batch */
 } qr_server_opts;
 
 typedef struct qr_server_done {

@@ -52,7 +52,8 @@ class QrBatchItem(ctypes.Structure):
 
 class ServerOpts(ctypes.Structure):
     _fields_ = [("hbm_budget", _i64), ("max_batch", _i64), ("max_pending", _i64),
-                ("stage_bytes", _i64), ("keep_factors", ctypes.c_int32), ("pad", ctypes.c_int32)]
+                ("stage_bytes", _i64), ("keep_factors", ctypes.c_int32),
+                ("precision", ctypes.c_int32)]
 
 
 class ServerDone(ctypes.Structure):
@@ -112,6 +113,10 @@ def lib():
         L.qr_lstsq_batched.argtypes = [_vp, _vp, _i64, ctypes.POINTER(QrBatchItem),
                                        ctypes.POINTER(QrOpts), ctypes.POINTER(ctypes.c_int32)]
         L.qr_lstsq_batched.restype = st
+        L.qr_lstsq_batched_ex.argtypes = [_vp, _vp, _i64, ctypes.POINTER(QrBatchItem),
+                                          ctypes.POINTER(QrOpts), ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.POINTER(ctypes.c_int32)]
+        L.qr_lstsq_batched_ex.restype = st
         L.qr_server_create.argtypes = [_vp, ctypes.POINTER(ServerOpts), ctypes.POINTER(_vp)]
         L.qr_server_create.restype = st
         L.qr_server_destroy.argtypes = [_vp]
@@ -350,11 +355,13 @@ class Handle:
                    info.backward_error) if want_info else None
         return st, out
 
-    def lstsq_batched(self, As, Bs, opts: Optional[QrOpts] = None, want_status: bool = True):
-        """Batched least squares in one launch: for each i, A_i is overwritten
-        (R in its upper triangle) and B_i[:n_i] receives the solution.  Returns
-        (status, per-problem statuses or None); raises on errors other than
-        ESINGULAR."""
+    def lstsq_batched(self, As, Bs, opts: Optional[QrOpts] = None, want_status: bool = True,
+                      want_iters: bool = False):
+        """Batched least squares: for each i, A_i is overwritten (R in its
+        upper triangle) and B_i[:n_i] receives the solution.  Returns (status,
+        per-problem statuses or None) and, with want_iters, also the
+        per-problem refinement iterations (-1: solved again in FP64); raises
+        on errors other than ESINGULAR."""
         if len(As) != len(Bs):
             raise ValueError("As and Bs differ in length")
         items = (QrBatchItem * max(len(As), 1))()
@@ -363,12 +370,15 @@ class Handle:
             bp, ldb = _mat(B, "B")
             items[i] = QrBatchItem(A.shape[0], A.shape[1], B.shape[1], ap.value, lda, bp.value, ldb)
         stat = (ctypes.c_int32 * max(len(As), 1))()
-        st = lib().qr_lstsq_batched(self._h, _stream(), len(As), items,
-                                    ctypes.byref(opts) if opts else None,
-                                    stat if want_status else None)
+        its = (ctypes.c_int32 * max(len(As), 1))()
+        st = lib().qr_lstsq_batched_ex(self._h, _stream(), len(As), items,
+                                       ctypes.byref(opts) if opts else None,
+                                       stat if want_status else None,
+                                       its if want_iters else None)
         if st not in (OK, ESINGULAR):
             self._check(st)
-        return st, (list(stat)[:len(As)] if want_status else None)
+        out = (st, (list(stat)[:len(As)] if want_status else None))
+        return out + (list(its)[:len(As)],) if want_iters else out
 
 
 def _host(x, name: str):
@@ -399,10 +409,10 @@ class Server:
     loop).  Host inputs are referenced until their request is reported done."""
 
     def __init__(self, handle: Handle, hbm_budget=0, max_batch=0, max_pending=0,
-                 stage_bytes=0, keep_factors=False):
+                 stage_bytes=0, keep_factors=False, precision=0):
         self._handle = handle
         o = ServerOpts(hbm_budget, max_batch, max_pending, stage_bytes,
-                       1 if keep_factors else 0, 0)
+                       1 if keep_factors else 0, precision)
         self._s = _vp()
         handle._check(lib().qr_server_create(handle._h, ctypes.byref(o), ctypes.byref(self._s)))
         self._hold = {}

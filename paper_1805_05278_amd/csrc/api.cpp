@@ -476,7 +476,8 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
   return fail(h, MIQR_ENOCONV, "refinement did not reach 1e-13; FP64 result returned");
 }
 
-// Pinned host staging for `count` tasks and statuses.  Waits for the previous
+// Pinned host staging for `count` tasks and 2 `count` ints (statuses, then
+// refinement iterations).  Waits for the previous
 // upload out of the staging buffer before it may be rewritten.
 miqr_status ensure_pinned(miqr_handle h, int64_t count) {
   hipError_t e = hipSuccess;
@@ -496,7 +497,7 @@ miqr_status ensure_pinned(miqr_handle h, int64_t count) {
   const int64_t cap = std::max<int64_t>(count, 1024);
   e = hipHostMalloc((void**)&h->pin_tasks, batch_table_bytes(cap), hipHostMallocDefault);
   if (e == hipSuccess)
-    e = hipHostMalloc((void**)&h->pin_status, cap * sizeof(int32_t), hipHostMallocDefault);
+    e = hipHostMalloc((void**)&h->pin_status, 2 * cap * sizeof(int32_t), hipHostMallocDefault);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(h, MIQR_ENOMEM, "pinned staging allocation failed");
@@ -925,15 +926,20 @@ miqr_status qr_lstsq(miqr_handle h, void* stream, int64_t m, int64_t n, int64_t 
   return MIQR_OK;
 }
 
-miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
-                             const qr_batch_item* items, const qr_opts* o, int32_t* status) {
+miqr_status qr_lstsq_batched_ex(miqr_handle h, void* stream, int64_t count,
+                                const qr_batch_item* items, const qr_opts* o, int32_t* status,
+                                int32_t* iters) {
   if (!h) return MIQR_EINVAL;
   ProfScope prof_scope(h);
   h->err.clear();
   if (count < 0 || count > (int64_t)1 << 30 || (count > 0 && !items))
     return fail(h, MIQR_EINVAL, "bad count or items");
-  if (o && o->precision != MIQR_FP64)
-    return fail(h, MIQR_ENOTSUP, "batched least squares runs in FP64 only");
+  const int precision = o ? o->precision : MIQR_FP64;
+  if (precision != MIQR_FP64 && precision != MIQR_MIXED_FP32 && precision != MIQR_MIXED_BF16)
+    return fail(h, MIQR_EINVAL, "unknown precision");
+  const int prec = precision == MIQR_MIXED_FP32   ? kBlkF32
+                   : precision == MIQR_MIXED_BF16 ? kBlkBF16
+                                                  : kBlkF64;
   if (o && (o->normalize || o->Q)) return fail(h, MIQR_ENOTSUP, "batched lstsq takes no Q/normalize");
   int64_t rtot = 0;  // R (n x n) and C (n x nrhs) per problem, each 32-double aligned
   double bytes = 0.0, flops = 0.0;
@@ -955,7 +961,7 @@ miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
   if (hipSetDevice(h->device) != hipSuccess) return fail(h, MIQR_EHIP, "hipSetDevice");
   hipStream_t s = (hipStream_t)stream;
   const int64_t task_d = ((int64_t)batch_table_bytes(count) + 255) / 256 * 32;
-  const int64_t stat_d = (count * 4 + 255) / 256 * 32;
+  const int64_t stat_d = (2 * count * 4 + 255) / 256 * 32;
   miqr_status st = ensure_ws(h, (size_t)(task_d + stat_d + 32 + rtot) * sizeof(double));
   if (st != MIQR_OK) return st;
   st = ensure_pinned(h, count);
@@ -963,60 +969,122 @@ miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
   Arena ar{(double*)h->ws};
   BatchHeader* dtable = (BatchHeader*)ar.take(task_d);
   int* dstatus = (int*)ar.take(stat_d);
+  int* diters = dstatus + count;
   int* counter = (int*)ar.take(32);
   double* rbase = ar.take(rtot);
-  // Largest problems first (their cost is about blocks x columns steps), so
-  // the persistent grid ends with small problems and finishes evenly.
-  std::vector<int64_t> order((size_t)count);
-  for (int64_t i = 0; i < count; ++i) order[(size_t)i] = i;
-  auto cost = [&](int64_t i) {
-    return ((items[i].m + kBatchRows - 1) / kBatchRows + 1) * items[i].n;
-  };
-  std::stable_sort(order.begin(), order.end(),
-                   [&](int64_t a, int64_t b) { return cost(a) > cost(b); });
-  int64_t roff = 0;
-  BatchTask* ptasks = batch_tasks(h->pin_tasks);
-  h->pin_tasks->count = (int)count;
-  for (int64_t k = 0; k < count; ++k) {
-    const int64_t i = order[(size_t)k];
-    const qr_batch_item& it = items[i];
-    BatchTask t{};
-    t.A = it.A;
-    t.B = it.B;
-    t.R = rbase + roff;
-    roff += (it.n * it.n + 31) & ~int64_t(31);
-    t.C = rbase + roff;
-    roff += (it.n * it.nrhs + 31) & ~int64_t(31);
-    t.tau = nullptr;
-    t.lda = it.lda;
-    t.ldb = it.ldb;
-    t.m = (int)it.m;
-    t.n = (int)it.n;
-    t.nrhs = (int)it.nrhs;
-    t.flags = kTaskWriteR;
-    t.slot = (int)i;
-    ptasks[k] = t;
+  std::vector<int64_t> roff((size_t)count);
+  for (int64_t i = 0, off = 0; i < count; ++i) {
+    roff[(size_t)i] = off;
+    off += ((items[i].n * items[i].n + 31) & ~int64_t(31)) +
+           ((items[i].n * items[i].nrhs + 31) & ~int64_t(31));
   }
-  hipError_t e = hipMemcpyAsync(dtable, h->pin_tasks, batch_table_bytes(count),
-                                hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipEventRecord(h->table_ev, s);
-  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched upload");
-  batched_ls(s, dtable, counter, dstatus, batched_grid(h->device, (int)count), bytes, flops);
-  e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched launch");
-  if (!status) return MIQR_OK;
-  e = hipMemcpyAsync(h->pin_status, dstatus, count * sizeof(int32_t), hipMemcpyDeviceToHost, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched status");
+  // Enqueue the items of `sel` in precision p: tasks grouped by queue (the
+  // refinement kernel takes queues 1..3 as one contiguous range), largest
+  // problems first within each queue (their cost is about blocks x columns^2
+  // steps), so that every persistent grid ends with small problems.
+  auto launch = [&](const std::vector<int64_t>& sel, int p) -> miqr_status {
+    st = ensure_pinned(h, (int64_t)sel.size());
+    if (st != MIQR_OK) return st;
+    std::vector<BatchTask> tk(sel.size());
+    std::vector<int> q(sel.size());
+    for (size_t k = 0; k < sel.size(); ++k) {
+      const int64_t i = sel[k];
+      const qr_batch_item& it = items[i];
+      BatchTask& t = tk[k];
+      t = BatchTask{};
+      t.A = it.A;
+      t.B = it.B;
+      t.R = rbase + roff[(size_t)i];
+      t.C = t.R + ((it.n * it.n + 31) & ~int64_t(31));
+      t.lda = it.lda;
+      t.ldb = it.ldb;
+      t.m = (int)it.m;
+      t.n = (int)it.n;
+      t.nrhs = (int)it.nrhs;
+      t.flags = kTaskWriteR;
+      t.slot = (int)i;
+      q[k] = batch_queue(t);
+    }
+    std::vector<size_t> order(sel.size());
+    for (size_t k = 0; k < order.size(); ++k) order[k] = k;
+    auto cost = [&](size_t k) {
+      const double N = (double)tk[k].n + tk[k].nrhs;
+      return ((tk[k].m + kBatchRows - 1) / kBatchRows + 1) * N * N;
+    };
+    std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+      return q[a] != q[b] ? q[a] < q[b] : cost(a) > cost(b);
+    });
+    BatchHeader* hd = h->pin_tasks;
+    *hd = BatchHeader{};
+    BatchTask* pt = batch_tasks(hd);
+    hd->total = (int)sel.size();
+    for (size_t k = 0; k < order.size(); ++k) {
+      pt[k] = tk[order[k]];
+      hd->count[q[order[k]]]++;
+    }
+    for (int k = 1; k < kBatchQueues; ++k) hd->begin[k] = hd->begin[k - 1] + hd->count[k - 1];
+    hipError_t e = hipMemcpyAsync(dtable, hd, batch_table_bytes((int64_t)sel.size()),
+                                  hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipEventRecord(h->table_ev, s);
+    if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched upload");
+    BatchGrids g = batched_grids(h->device, p);
+    for (int k = 0; k < kBatchQueues; ++k) g.g[k] = std::min(g.g[k], hd->count[k]);
+    g.g[kBatchQueues] = std::min<int64_t>(g.g[kBatchQueues], (int64_t)sel.size());
+    batched_ls(s, dtable, counter, dstatus, diters, g, p, bytes, flops);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched launch");
+    return MIQR_OK;
+  };
+  auto fetch = [&]() -> miqr_status {
+    hipError_t e = hipMemcpyAsync(h->pin_status, dstatus, 2 * count * sizeof(int32_t),
+                                  hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return hip_fail(h, e, "qr_lstsq_batched status");
+    return MIQR_OK;
+  };
+  std::vector<int64_t> all((size_t)count);
+  for (int64_t i = 0; i < count; ++i) all[(size_t)i] = i;
+  st = launch(all, prec);
+  if (st != MIQR_OK) return st;
+  if (!status && !iters && prec == kBlkF64) return MIQR_OK;
+  st = fetch();
+  if (st != MIQR_OK) return st;
+  std::vector<int32_t> stv(h->pin_status, h->pin_status + count);
+  std::vector<int32_t> itv((size_t)count, 0);
+  if (prec != kBlkF64) {
+    // Problems whose refinement missed the target are solved again in FP64
+    // (their A and B were left as they were).
+    std::vector<int64_t> redo;
+    for (int64_t i = 0; i < count; ++i) {
+      itv[(size_t)i] = h->pin_status[count + i];
+      if (stv[(size_t)i] == kStatusNoConv) redo.push_back(i);
+    }
+    if (!redo.empty()) {
+      st = launch(redo, kBlkF64);
+      if (st != MIQR_OK) return st;
+      st = fetch();
+      if (st != MIQR_OK) return st;
+      for (int64_t i : redo) {
+        stv[(size_t)i] = h->pin_status[i];
+        itv[(size_t)i] = -1;
+      }
+    }
+  }
   int64_t bad = -1;
   for (int64_t i = 0; i < count; ++i) {
-    status[i] = h->pin_status[i];
-    if (status[i] != 0 && bad < 0) bad = i;
+    if (status) status[i] = stv[(size_t)i];
+    if (iters) iters[i] = itv[(size_t)i];
+    if (stv[(size_t)i] != 0 && bad < 0) bad = i;
   }
   if (bad >= 0)
     return fail(h, MIQR_ESINGULAR, "item " + std::to_string(bad) + ": R(" +
-                                       std::to_string(status[bad] - 1) + ") == 0");
+                                       std::to_string(stv[(size_t)bad] - 1) + ") == 0");
   return MIQR_OK;
+}
+
+miqr_status qr_lstsq_batched(miqr_handle h, void* stream, int64_t count,
+                             const qr_batch_item* items, const qr_opts* o, int32_t* status) {
+  return qr_lstsq_batched_ex(h, stream, count, items, o, status, nullptr);
 }
 
 }  // extern "C"

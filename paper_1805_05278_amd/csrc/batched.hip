@@ -29,7 +29,7 @@ namespace {
 constexpr int H = kBatchRows;
 
 __global__ void k_batch_reset(int* counter) {
-  if (threadIdx.x == 0) counter[0] = 0;
+  if (threadIdx.x < kBatchCounters) counter[threadIdx.x] = 0;
 }
 
 // Global-address-space views: loads and stores through them wait on the
@@ -252,8 +252,9 @@ __device__ int batch_solve(const BatchTask& t, double (*xbuf)[kBatchMaxRhs], int
 
 __global__ __launch_bounds__(kBatchThreads) void k_batched_ls(const BatchHeader* table,
                                                                  int* counter, int* status) {
-  const int count = __builtin_amdgcn_readfirstlane(table->count);
-  const BatchTask* tasks = (const BatchTask*)(table + 1);
+  const int count = __builtin_amdgcn_readfirstlane(table->count[0]);
+  const BatchTask* tasks =
+      (const BatchTask*)(table + 1) + __builtin_amdgcn_readfirstlane(table->begin[0]);
   __shared__ __align__(16) double ybuf[2][H];
   __shared__ double tbuf[2][2];
   __shared__ double xbuf[2][kBatchMaxRhs];
@@ -286,7 +287,12 @@ __global__ __launch_bounds__(kBatchThreads) void k_batched_ls(const BatchHeader*
 
 }  // namespace
 
-int batched_grid(int device, int count) {
+int batched_blk_grid(int device, int prec, int queue);
+void batched_blk_launch(hipStream_t s, const BatchHeader* table, int queue, int* counter,
+                        int* status, int* iters, int grid, int prec);
+
+BatchGrids batched_grids(int device, int prec) {
+  BatchGrids g{};
   int cus = 256;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
     cus = 256;
@@ -295,16 +301,23 @@ int batched_grid(int device, int count) {
           hipSuccess ||
       per < 1)
     per = 1;
-  const long long g = (long long)cus * per;
-  return (int)(count < g ? count : g);
+  g.g[0] = cus * per;
+  for (int k = 1; k <= kBatchQueues; ++k) g.g[k] = batched_blk_grid(device, prec, k);
+  return g;
 }
 
-void batched_ls(hipStream_t s, const BatchHeader* table, int* counter, int* status, int grid,
-                double bytes, double flops) {
-  if (grid <= 0) return;
+void batched_ls(hipStream_t s, const BatchHeader* table, int* counter, int* status, int* iters,
+                const BatchGrids& grids, int prec, double bytes, double flops) {
   hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counter);
   TimedLaunch tl(s, "batched_ls", bytes, flops);
-  hipLaunchKernelGGL(k_batched_ls, dim3(grid), dim3(kBatchThreads), 0, s, table, counter, status);
+  // Largest problems first: the queues of more tiles per wave hold them.
+  for (int k = kBatchQueues - 1; k >= 1; --k)
+    batched_blk_launch(s, table, k, counter, status, iters, grids.g[k], prec);
+  if (prec != kBlkF64)
+    batched_blk_launch(s, table, kBatchQueues, counter, status, iters, grids.g[kBatchQueues], prec);
+  if (grids.g[0] > 0)
+    hipLaunchKernelGGL(k_batched_ls, dim3(grids.g[0]), dim3(kBatchThreads), 0, s, table, counter,
+                       status);
 }
 
 }  // namespace miqr

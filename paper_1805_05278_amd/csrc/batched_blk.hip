@@ -1,0 +1,940 @@
+// Batched least squares, blocked form: one workgroup of four waves per
+// problem, popped from a device queue by a persistent grid.
+//
+// As in the column sweep, min ||B - A X|| (A m x n, nrhs right-hand sides)
+// is solved by Householder QR of [A | B] (N = n + nrhs columns) with a flat
+// TSQR sweep over 64-row blocks (the TSQR of Sec. 5 / App. C.1 with a chain
+// as its tree): the running R (n x N) is stacked over each block X and
+// [R; X] is reduced.  Here the block's reflectors are taken sixteen at a
+// time (a panel) in the compact WY form of Sec. 2.3.  The reflector of
+// column j is v = [e_j; y] (R is upper triangular), so the panel's
+// V^T V = I + Y^T Y, its T follows the Sec. 2.3 recurrence on the Gram
+// entries y_i . y_j, and it updates each sixteen-column tile c right of it by
+//   W = R[panel rows, c] + Y^T X[:, c],   W' = T^T W,
+//   R[panel rows, c] -= W',   X[:, c] -= Y W',
+// three products on MFMA.
+//
+// Register layout: tile c of the block lives in wave c mod 4; lane l
+// (q = l / 16, cl = l % 16) holds rows 16 t + rho(q, r) (t, r = 0..3) of
+// column 16 c + cl, rho being the row map of the MFMA accumulator.  The tile
+// is therefore both the B operand of Y^T X (the contraction over the block's
+// rows runs in the order the registers hold them, with Y read in that same
+// order) and the accumulator of X -= Y W', with no data movement.  R stays in
+// global memory (L2): tile (p, c) is read and written once per block, always
+// by the wave that owns column tile c.
+//
+// A panel is factored by the wave that owns its tile, column by column
+// (dlarfg sign rule; norm, beta and tau in FP64): the pivot column reaches
+// the other lanes through LDS, dot products are per-lane partial sums and one
+// cross-row sum in registers (v_permlane16/32_swap), and the same sums give
+// the Gram entries of T.  Look-ahead: the owner of panel p + 1 updates that
+// tile first and factors it while the other waves still apply panel p, so a
+// panel costs one barrier.
+//
+// Precisions: FP64 throughout (FP64 MFMA), or a working copy of the block in
+// FP32 with Y^T X and Y W' on FP32 MFMA or on BF16 MFMA with FP32
+// accumulation; reflector generation, T and R stay in FP64 and T^T W runs on
+// FP32 MFMA.  The mixed forms then refine each solution in FP64 against the
+// original A and B: conjugate gradients on the normal equations with R as
+// preconditioner (CGLS on min ||b - (A R^-1) y||, x = R^-1 y), the residual
+// b - A x recomputed from A each iteration, until every right-hand side's
+// backward error ||A^T r|| / (||A||_F (||A||_F ||x|| + ||r||)) is at most
+// 5e-14 (the 1e-13 gate with a margin).  A and B are only written once that
+// holds; otherwise the problem
+// reports kStatusNoConv with A and B intact, for an FP64 solve.
+#include <climits>
+
+#include "batched.h"
+#include "common.h"
+
+namespace miqr {
+namespace {
+
+constexpr int H = kBatchRows;
+constexpr int NW = kBlkWaves;
+constexpr int NT = 64 * NW;
+constexpr int KG = 4;  // right-hand sides refined together
+// Refinement target: half the 1e-13 gate, a margin for the rounding of the
+// estimate itself (another FP64 evaluation of ||A^T r|| differs by about
+// u sqrt(m) ||A|| ||r||).
+constexpr double kRefineTol = 5e-14;
+constexpr int kRefineMaxIt = 40;
+
+static_assert(NW == 4, "tile-to-wave map assumes four waves");
+static_assert(kBatchMaxCols <= 2 * NT, "a thread owns at most two rows of R");
+
+typedef __attribute__((address_space(1))) double gdouble;
+__device__ __forceinline__ gdouble* gp(double* p) { return (gdouble*)p; }
+__device__ __forceinline__ const gdouble* gp(const double* p) { return (const gdouble*)p; }
+
+typedef short s4 __attribute__((ext_vector_type(4)));
+
+template <int P>
+struct Prec {
+  typedef float W;
+  typedef f4 V;
+};
+template <>
+struct Prec<kBlkF64> {
+  typedef double W;
+  typedef d4 V;
+};
+
+// Row map of the 16x16 MFMA accumulators: register r of lane group q holds
+// row rho(q, r); the FP64 output interleaves the lane groups, the FP32
+// outputs stack them.  rho_q / rho_r invert it.
+template <int P>
+__device__ __forceinline__ constexpr int rho(int q, int r) {
+  return P == kBlkF64 ? q + 4 * r : 4 * q + r;
+}
+template <int P>
+__device__ __forceinline__ constexpr int rho_q(int v) {
+  return P == kBlkF64 ? (v & 3) : (v >> 2);
+}
+template <int P>
+__device__ __forceinline__ constexpr int rho_r(int v) {
+  return P == kBlkF64 ? (v >> 2) : (v & 3);
+}
+
+// 16x16x4 MFMA of the working type: a = A[l % 16][l / 16], b = B[l / 16][l % 16].
+__device__ __forceinline__ d4 mma(double a, double b, d4 c) { return mfma64(a, b, c); }
+__device__ __forceinline__ f4 mma(float a, float b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Round to nearest even BF16 (finite inputs).
+__device__ __forceinline__ short to_bf16(float f) {
+  unsigned u = __float_as_uint(f);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+__device__ __forceinline__ s4 pack_bf16(f4 v) {
+  s4 o;
+  o[0] = to_bf16(v[0]);
+  o[1] = to_bf16(v[1]);
+  o[2] = to_bf16(v[2]);
+  o[3] = to_bf16(v[3]);
+  return o;
+}
+// 16x16x16 BF16 MFMA: a = A[l % 16][4 (l / 16) + j], b = B[4 (l / 16) + j][l % 16].
+__device__ __forceinline__ f4 mma_bf16(f4 a, f4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(pack_bf16(a), pack_bf16(b), c, 0, 0, 0);
+}
+
+__device__ __forceinline__ unsigned lo32(double v) {
+  return (unsigned)(unsigned long long)__double_as_longlong(v);
+}
+__device__ __forceinline__ unsigned hi32(double v) {
+  return (unsigned)((unsigned long long)__double_as_longlong(v) >> 32);
+}
+__device__ __forceinline__ double join(unsigned lo, unsigned hi) {
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// Sum over the four lanes cl, cl + 16, cl + 32, cl + 48: rows paired by
+// v_permlane16_swap, then halves by v_permlane32_swap; each swap leaves one
+// copy holding the lower partner in both places and the other the upper, so
+// every lane forms the same sums in the same order.
+__device__ __forceinline__ double rows_sum(double v) {
+  {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo32(v), lo32(v), false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi32(v), hi32(v), false, false);
+    v = join(l[0], h[0]) + join(l[1], h[1]);
+  }
+  {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo32(v), lo32(v), false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi32(v), hi32(v), false, false);
+    v = join(l[0], h[0]) + join(l[1], h[1]);
+  }
+  return v;
+}
+
+__device__ __forceinline__ double readlane(double v, int lane) {
+  return join((unsigned)__builtin_amdgcn_readlane((int)lo32(v), lane),
+              (unsigned)__builtin_amdgcn_readlane((int)hi32(v), lane));
+}
+
+// The lane index through an empty asm: addresses, masks and row numbers made
+// from it are then computed where they are used.  Otherwise the compiler
+// hoists them out of the sweep's loops as invariants and holds dozens of
+// them in registers for the whole problem, spilling the tiles.
+__device__ __forceinline__ int lane_id() {
+  int l = threadIdx.x & 63;
+  asm volatile("" : "+v"(l));
+  return l;
+}
+
+template <typename W>
+struct FactorLds {
+  W ya[2][4][4][16][4];  // Y by accumulator position: [buf][t][q][cl][r] = Y[16 t + rho(q, r)][cl]
+  W yt[2][4][16][4][4];  // Y as the A operand of Y W': [buf][t][i][q][r] = Y[16 t + i][rho(q, r)]
+  W ts[2][16][4][4];     // T: [buf][j][q][r] = T[rho(q, r)][j]
+  W piv[4][4][4];        // the pivot column: [t][q][r]
+};
+template <typename W>
+struct BlkLds {
+  FactorLds<W> f;
+  double gram[16][17];  // y_i . y_j, i < j, of the current panel
+  double tau[2][16];
+  double z[2][8];
+  int idx, sing;
+};
+struct RefineLds {
+  double v[kBatchMaxCols * KG];  // a vector of length n per right-hand side, [row][rhs]
+  double r[kBatchMaxCols * KG];  // a row chunk of the residual, then A^T r, [row][rhs]
+  double red[NW][KG];
+  double z[2][8];
+  int idx, sing;
+};
+
+__device__ __forceinline__ const double* src_col(const BatchTask& t, int col) {
+  return col < t.n ? t.A + (int64_t)col * t.lda : t.B + (int64_t)(col - t.n) * t.ldb;
+}
+__device__ __forceinline__ double* r_col(const BatchTask& t, int col) {
+  return col < t.n ? t.R + (int64_t)col * t.n : t.C + (int64_t)(col - t.n) * t.n;
+}
+
+// Tile (p, c) of the running R (rows 16 p.., columns 16 c.. of [R | C]) in
+// accumulator order; zero when `zero` (before the first block) and outside
+// n x N.
+template <int P>
+__device__ __forceinline__ void load_r(const BatchTask& t, int p, int c, bool zero, double (&rv)[4]) {
+  const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
+  const int col = 16 * c + cl;
+  const bool in = !zero && col < t.n + t.nrhs;
+  const gdouble* rc = gp(r_col(t, in ? col : 0));
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * p + rho<P>(q, r);
+    rv[r] = (in && row < t.n) ? rc[row] : 0.0;
+  }
+}
+template <int P>
+__device__ __forceinline__ void store_r(const BatchTask& t, int p, int c, const double (&rv)[4]) {
+  const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
+  const int col = 16 * c + cl;
+  if (col >= t.n + t.nrhs) return;
+  gdouble* rc = gp(r_col(t, col));
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const int row = 16 * p + rho<P>(q, r);
+    if (row < t.n) rc[row] = rv[r];
+  }
+}
+
+// Tile c of the block at row r0 of [A | B], in the working precision.
+template <int P>
+__device__ __forceinline__ void load_tile(const BatchTask& t, int r0, int c,
+                                          typename Prec<P>::V (&x)[4]) {
+  using W = typename Prec<P>::W;
+  const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
+  const int col = 16 * c + cl;
+  const bool in = col < t.n + t.nrhs;
+  const gdouble* src = gp(src_col(t, in ? col : 0));
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int row = r0 + 16 * tt + rho<P>(q, r);
+      x[tt][r] = (W)((in && row < t.m) ? src[row] : 0.0);
+    }
+}
+
+// Householder QR of panel p (columns 16 p .. 16 p + pw - 1) of [R; X] by the
+// wave that owns its tile x.  Leaves the reflector tails Y in x's panel
+// columns (the tile's other columns, right-hand sides, are updated), Y and T
+// in LDS buffer p & 1, the diagonal tile of R in global memory, and tau in
+// LDS (and in t.tau for kept factors).
+template <int P>
+__device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>::V (&x)[4],
+                             BlkLds<typename Prec<P>::W>& S) {
+  using W = typename Prec<P>::W;
+  using V = typename Prec<P>::V;
+  const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
+  const int n = t.n;
+  const int pw = min(16, n - 16 * p);
+  const int b = p & 1;
+  const bool keep = (t.flags & kTaskKeep) != 0;
+  FactorLds<W>& F = S.f;
+  double rd[4];
+  load_r<P>(t, p, p, bk == 0, rd);
+  double mysc = 0.0;  // scale of this lane's column reflector (y = sc x)
+  // A loop over the columns (not unrolled: unrolled, the per-column lane
+  // masks are loop invariants that the compiler keeps live across the whole
+  // sweep).  Row jj of the diagonal R tile sits in register rho_r(jj) of lane
+  // group rho_q(jj); registers are picked by selects.
+#pragma unroll 1
+  for (int jj = 0; jj < pw; ++jj) {
+    const int qj = rho_q<P>(jj), rj = rho_r<P>(jj);
+    // Squares of every lane's column; lane jj's sum is the pivot's.
+    W s0 = 0, s1 = 0;
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      s0 += x[tt][0] * x[tt][0] + x[tt][2] * x[tt][2];
+      s1 += x[tt][1] * x[tt][1] + x[tt][3] * x[tt][3];
+    }
+    const double sig2 = readlane(rows_sum((double)s0 + (double)s1), jj);
+    const double rdj = rj == 0 ? rd[0] : (rj == 1 ? rd[1] : (rj == 2 ? rd[2] : rd[3]));
+    const double alpha = readlane(rdj, 16 * qj + jj);
+    double tau = 0.0, beta = alpha, sc = 0.0;
+    if (sig2 != 0.0) {
+      const double nrm = sqrt(alpha * alpha + sig2);
+      beta = alpha >= 0.0 ? -nrm : nrm;
+      tau = (beta - alpha) / beta;
+      sc = 1.0 / (alpha - beta);
+    }
+    if (cl == jj) {
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) *(V*)&F.piv[tt][q][0] = x[tt];
+    }
+    __builtin_amdgcn_wave_barrier();
+    W d0 = 0, d1 = 0;
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      const V pv = *(const V*)&F.piv[tt][q][0];
+      d0 += pv[0] * x[tt][0] + pv[2] * x[tt][2];
+      d1 += pv[1] * x[tt][1] + pv[3] * x[tt][3];
+    }
+    // w = R[j, cl] + y_j . x_cl (the R entry enters through its row group).
+    const bool rowj = q == qj;
+    const double z = sc * ((double)d0 + (double)d1) + (rowj ? rdj : 0.0);
+    const double w = rows_sum(z);
+    if (q == 0 && cl < jj) S.gram[cl][jj] = mysc * w;
+    // New R[j, cl]: beta on the diagonal, R[j, cl] - tau w right of it.
+    double rnew = rdj;
+    if (tau != 0.0 && cl > jj) {
+      // The pivot column is read from LDS again rather than held across
+      // the cross-row sum (register pressure).
+      const W f = (W)(tau * w * sc);
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) x[tt] -= f * *(const V*)&F.piv[tt][q][0];
+      rnew = rdj - tau * w;
+    }
+    if (cl == jj) {
+      mysc = sc;
+      rnew = beta;
+    }
+    if (rowj) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) rd[r] = (r == rj) ? rnew : rd[r];
+    }
+    if (lane == 0) {
+      S.tau[b][jj] = tau;
+      if (keep) gp(t.tau)[(int64_t)bk * n + 16 * p + jj] = tau;
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  // Y in the panel columns; zero for the tile's other columns in the LDS copies.
+  const bool acol = cl < pw;
+  const W ys = acol ? (W)mysc : (W)0;
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) {
+    const V y = x[tt] * ys;
+    if (acol) x[tt] = y;
+    *(V*)&F.ya[b][tt][q][cl][0] = y;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) F.yt[b][tt][rho<P>(q, r)][rho_q<P>(cl)][rho_r<P>(cl)] = y[r];
+  }
+  __builtin_amdgcn_wave_barrier();
+  // T (Sec. 2.3 recurrence): T[i][i] = tau_i, T[i][j] = -tau_j sum_k T[i][k]
+  // G[k][j] for j > i.  Row i = cl is shared by the four lanes of its column,
+  // lane group q holding T[i][rho(q, r)]; each column j is one cross-row sum.
+  double tr[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 1
+  for (int j = 0; j < pw; ++j) {
+    double a = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = rho<P>(q, r);
+      if (k < j) a += tr[r] * S.gram[k][j];
+    }
+    a = rows_sum(a);
+    const double tj = S.tau[b][j];
+    const double v = (j == cl) ? tj : ((j > cl) ? -tj * a : 0.0);
+    const int qj = rho_q<P>(j), rj = rho_r<P>(j);
+    if (q == qj) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) tr[r] = (r == rj) ? v : tr[r];
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) F.ts[b][rho<P>(q, r)][rho_q<P>(cl)][rho_r<P>(cl)] = (W)tr[r];
+  store_r<P>(t, p, p, rd);
+}
+
+// Update of tile x (column tile c) by panel p.
+template <int P>
+__device__ __forceinline__ void update_tile(const BatchTask& t, int p, int c, bool first,
+                                            typename Prec<P>::V (&x)[4],
+                                            const FactorLds<typename Prec<P>::W>& F) {
+  using W = typename Prec<P>::W;
+  using V = typename Prec<P>::V;
+  const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
+  const int b = p & 1;
+  // Y and T are read from LDS for each tile rather than held across the
+  // wave's tiles (register pressure): the empty asm keeps the compiler from
+  // merging the reads of consecutive tile updates.
+  asm volatile("" ::: "memory");
+  double ro[4];
+  load_r<P>(t, p, c, first, ro);
+  V acc = {};
+  if constexpr (P == kBlkBF16) {
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) acc = mma_bf16(*(const V*)&F.ya[b][tt][q][cl][0], x[tt], acc);
+  } else {
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      const V ya = *(const V*)&F.ya[b][tt][q][cl][0];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc = mma(ya[r], x[tt][r], acc);
+    }
+  }
+  V wv;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) wv[r] = (W)(ro[r] + (double)acc[r]);
+  const V tv = *(const V*)&F.ts[b][cl][q][0];
+  V w2 = {};
+#pragma unroll
+  for (int r = 0; r < 4; ++r) w2 = mma(tv[r], wv[r], w2);
+#pragma unroll
+  for (int r = 0; r < 4; ++r) ro[r] -= (double)w2[r];
+  store_r<P>(t, p, c, ro);
+  const V nw = -w2;
+  asm volatile("" ::: "memory");
+  if constexpr (P == kBlkBF16) {
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) x[tt] = mma_bf16(*(const V*)&F.yt[b][tt][cl][q][0], nw, x[tt]);
+  } else {
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) {
+      const V yt = *(const V*)&F.yt[b][tt][cl][q][0];
+#pragma unroll
+      for (int r = 0; r < 4; ++r) x[tt] = mma(yt[r], nw[r], x[tt]);
+    }
+  }
+}
+
+// The owner's step for panel pn = p + 1 held in slot `slot`: update by panel
+// p (if any), then factor.  Recursion over the slots keeps every register
+// index a constant.
+template <int P, int I, int MAXT>
+__device__ __forceinline__ void own_panel(const BatchTask& t, int p, int slot, int bk,
+                                          typename Prec<P>::V (&x)[MAXT][4],
+                                          BlkLds<typename Prec<P>::W>& S) {
+  if constexpr (I < MAXT) {
+    if (slot == I) {
+      if (p >= 0) update_tile<P>(t, p, p + 1, bk == 0, x[I], S.f);
+      panel_factor<P>(t, p + 1, bk, x[I], S);
+    } else {
+      own_panel<P, I + 1, MAXT>(t, p, slot, bk, x, S);
+    }
+  }
+}
+
+// The sweep over the row blocks; leaves R and C (the top n rows of Q^T B) in
+// t.R / t.C.
+template <int P, int MAXT>
+__device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
+  using V = typename Prec<P>::V;
+  const int w = threadIdx.x >> 6;
+  const int n = t.n, N = n + t.nrhs;
+  const int CT = (N + 15) >> 4, PT = (n + 15) >> 4;
+  const int nblk = (t.m + H - 1) / H;
+  const bool keep = (t.flags & kTaskKeep) != 0;
+  V x[MAXT][4];
+  for (int bk = 0; bk < nblk; ++bk) {
+    const bool first = bk == 0;
+#pragma unroll
+    for (int i = 0; i < MAXT; ++i) {
+      const int c = w + NW * i;
+      if (c < CT) load_tile<P>(t, bk * H, c, x[i]);
+    }
+    for (int p = -1; p < PT; ++p) {
+      if (p >= 0) __syncthreads();  // Y, T of panel p published
+      const int pn = p + 1;
+      // Look-ahead: the owner of panel pn brings its tile up to date first
+      // and factors it.
+      if (pn < PT && w == (pn & 3)) own_panel<P, 0, MAXT>(t, p, pn >> 2, bk, x, S);
+      if (p >= 0) {
+#pragma unroll
+        for (int i = 0; i < MAXT; ++i) {
+          const int c = w + NW * i;
+          if (c > p && c < CT && (c != pn || pn >= PT)) update_tile<P>(t, p, c, first, x[i], S.f);
+        }
+      }
+    }
+    if (keep) {
+      // Kept factors: the reflector tails of the block into A's rows.
+      const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
+#pragma unroll
+      for (int i = 0; i < MAXT; ++i) {
+        const int col = 16 * (w + NW * i) + cl;
+        if (col < n) {
+          gdouble* dst = gp(t.A + (int64_t)col * t.lda);
+#pragma unroll
+          for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+              const int row = bk * H + 16 * tt + rho<P>(q, r);
+              if (row < t.m) dst[row] = (double)x[i][tt][r];
+            }
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// Sum over the workgroup of KK values per thread; every thread receives the
+// same totals (butterfly sums within each wave, then the wave totals in
+// order).
+template <int KK>
+__device__ __forceinline__ void wg_sum(double (&v)[KK], double (*red)[KG]) {
+  static_assert(KK <= KG, "reduction width");
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < KK; ++k) v[k] = wave_sum(v[k]);
+  if (lane == 0)
+#pragma unroll
+    for (int k = 0; k < KK; ++k) red[w][k] = v[k];
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < KK; ++k) v[k] = (red[0][k] + red[1][k]) + (red[2][k] + red[3][k]);
+  __syncthreads();
+}
+
+// R z = v in place by back substitution (R upper triangular, n x n in t.R);
+// thread l holds rows l and l + NT of KK right-hand sides.  One barrier per
+// row; the next column of R is loaded during the current step.
+template <int KK>
+__device__ void backsub(const BatchTask& t, double (&v)[2][KK], double (*zb)[8]) {
+  const int l = threadIdx.x, n = t.n, l1 = l + NT;
+  const gdouble* R = gp(t.R);
+  double c0 = (l < n) ? R[(int64_t)(n - 1) * n + l] : 0.0;
+  double c1 = (l1 < n) ? R[(int64_t)(n - 1) * n + l1] : 0.0;
+  for (int i = n - 1; i >= 0; --i) {
+    const int s = i & 1;
+    const double a0 = c0, a1 = c1;  // R[l][i], R[l1][i]
+    if (i >= 1) {
+      c0 = (l < i) ? R[(int64_t)(i - 1) * n + l] : 0.0;
+      c1 = (l1 < i) ? R[(int64_t)(i - 1) * n + l1] : 0.0;
+    }
+    if (l == i)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) {
+        v[0][k] = v[0][k] / a0;
+        zb[s][k] = v[0][k];
+      }
+    if (l1 == i)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) {
+        v[1][k] = v[1][k] / a1;
+        zb[s][k] = v[1][k];
+      }
+    __syncthreads();
+    if (l < i)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) v[0][k] -= a0 * zb[s][k];
+    if (l1 < i)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) v[1][k] -= a1 * zb[s][k];
+  }
+  __syncthreads();
+}
+
+// R^T z = v in place by forward substitution (row i of R enters step i).
+template <int KK>
+__device__ void fwdsub_t(const BatchTask& t, double (&v)[2][KK], double (*zb)[8]) {
+  const int l = threadIdx.x, n = t.n, l1 = l + NT;
+  const gdouble* R = gp(t.R);
+  double c0 = (l < n) ? R[(int64_t)l * n] : 0.0;
+  double c1 = (l1 < n) ? R[(int64_t)l1 * n] : 0.0;
+  for (int i = 0; i < n; ++i) {
+    const int s = i & 1;
+    const double a0 = c0, a1 = c1;  // R[i][l], R[i][l1]
+    if (i + 1 < n) {
+      c0 = (l > i && l < n) ? R[(int64_t)l * n + i + 1] : 0.0;
+      c1 = (l1 > i && l1 < n) ? R[(int64_t)l1 * n + i + 1] : 0.0;
+    }
+    if (l == i)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) {
+        v[0][k] = v[0][k] / a0;
+        zb[s][k] = v[0][k];
+      }
+    if (l1 == i)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) {
+        v[1][k] = v[1][k] / a1;
+        zb[s][k] = v[1][k];
+      }
+    __syncthreads();
+    if (l > i && l < n)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) v[0][k] -= a0 * zb[s][k];
+    if (l1 > i && l1 < n)
+#pragma unroll
+      for (int k = 0; k < KK; ++k) v[1][k] -= a1 * zb[s][k];
+  }
+  __syncthreads();
+}
+
+// First zero diagonal entry of R, or INT_MAX.
+__device__ int zero_diagonal(const BatchTask& t, int* sing) {
+  if (threadIdx.x == 0) *sing = INT_MAX;
+  __syncthreads();
+  for (int row = threadIdx.x; row < t.n; row += NT)
+    if (gp(t.R)[(int64_t)row * t.n + row] == 0.0) atomicMin(sing, row);
+  __syncthreads();
+  const int s = *sing;
+  __syncthreads();
+  return s;
+}
+
+// Rows l, l + NT of right-hand sides k0.. of an n x nrhs matrix (ld) into v.
+template <int KK>
+__device__ __forceinline__ void load_rows(const double* M, int64_t ld, int n, int k0, int kn,
+                                          double (&v)[2][KK]) {
+  const int l = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+      const int row = l + h * NT;
+      v[h][k] = (row < n && k0 + k < kn) ? gp(M)[(int64_t)(k0 + k) * ld + row] : 0.0;
+    }
+}
+template <int KK>
+__device__ __forceinline__ void store_rows(double* M, int64_t ld, int n, int k0, int kn,
+                                           const double (&v)[2][KK]) {
+  const int l = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h)
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+      const int row = l + h * NT;
+      if (row < n && k0 + k < kn) gp(M)[(int64_t)(k0 + k) * ld + row] = v[h][k];
+    }
+}
+
+// FP64: back substitution R x = c[0:n]; x into B's top rows (and X).  If some
+// R_jj == 0, B's top rows receive c and the status is j + 1.
+__device__ int finish_f64(const BatchTask& t, BlkLds<double>& S) {
+  const int sing = zero_diagonal(t, &S.sing);
+  for (int k0 = 0; k0 < t.nrhs; k0 += 8) {
+    double v[2][8];
+    load_rows<8>(t.C, t.n, t.n, k0, t.nrhs, v);
+    if (sing == INT_MAX) backsub<8>(t, v, S.z);
+    store_rows<8>(t.B, t.ldb, t.n, k0, t.nrhs, v);
+    if (t.X) store_rows<8>(t.X, t.n, t.n, k0, t.nrhs, v);
+  }
+  return sing == INT_MAX ? 0 : sing + 1;
+}
+
+// v (rows l, l + NT) into the LDS vector, [row][rhs].
+__device__ __forceinline__ void put_vector(const BatchTask& t, const double (&v)[2][KG], double* dst) {
+  const int l = threadIdx.x;
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int row = l + h * NT;
+    if (row < t.n)
+#pragma unroll
+      for (int k = 0; k < KG; ++k) dst[row * KG + k] = v[h][k];
+  }
+}
+
+// Column tiles per wave for A^T r (n <= kBatchMaxCols).
+constexpr int RT = (kBatchMaxCols + 16 * NW - 1) / (16 * NW);
+
+// FP64 refinement of right-hand sides k0 .. k0 + KG - 1 (see the file
+// comment).  Returns the iterations used, or -1 if the target was not met.
+__device__ int refine_group(const BatchTask& t, RefineLds& S, double anorm, int k0) {
+  const int l = threadIdx.x, w = l >> 6;
+  const int m = t.m, n = t.n;
+  const int kn = min(KG, t.nrhs - k0);
+  const gdouble* A = gp(t.A);
+  const gdouble* B = gp(t.B);
+  double xv[2][KG], pv[2][KG], sv[2][KG];
+  load_rows<KG>(t.C, t.n, n, k0, t.nrhs, xv);
+  backsub<KG>(t, xv, S.z);
+  double gam[KG] = {};
+  double h1 = 0.0, h2 = 0.0, h3 = 0.0, h4 = 0.0;  // worst of the last four iterations
+  for (int it = 0;; ++it) {
+    // r = b - A x row by row; u = A^T r from the same chunk (lane (q, cl)
+    // sums column 16 c + cl over the chunk rows = q mod 4).
+    put_vector(t, xv, S.v);
+    __syncthreads();
+    double rr[KG] = {};
+    double u[RT][KG] = {};
+    for (int r0 = 0; r0 < m; r0 += NT) {
+      const int i = r0 + l;
+      double acc[KG] = {};
+      if (i < m) {
+        for (int j = 0; j < n; ++j) {
+          const double a = A[(int64_t)j * t.lda + i];
+#pragma unroll
+          for (int k = 0; k < KG; ++k) acc[k] += a * S.v[j * KG + k];
+        }
+#pragma unroll
+        for (int k = 0; k < KG; ++k)
+          acc[k] = (k < kn ? B[(int64_t)(k0 + k) * t.ldb + i] : 0.0) - acc[k];
+      }
+#pragma unroll
+      for (int k = 0; k < KG; ++k) {
+        S.r[l * KG + k] = acc[k];
+        rr[k] += acc[k] * acc[k];
+      }
+      __syncthreads();
+      const int rows = min(NT, m - r0);
+      const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
+#pragma unroll
+      for (int ii = 0; ii < RT; ++ii) {
+        const int col = 16 * (w + NW * ii) + cl;
+        if (col < n) {
+          const gdouble* ac = A + (int64_t)col * t.lda + r0;
+          for (int s = q; s < rows; s += 4) {
+            const double a = ac[s];
+#pragma unroll
+            for (int k = 0; k < KG; ++k) u[ii][k] += a * S.r[s * KG + k];
+          }
+        }
+      }
+      __syncthreads();
+    }
+    {
+      const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
+#pragma unroll
+      for (int ii = 0; ii < RT; ++ii) {
+        const int col = 16 * (w + NW * ii) + cl;
+#pragma unroll
+        for (int k = 0; k < KG; ++k) {
+          const double s = rows_sum(u[ii][k]);
+          if (q == 0 && col < n) S.r[col * KG + k] = s;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int row = l + h * NT;
+#pragma unroll
+      for (int k = 0; k < KG; ++k) sv[h][k] = row < n ? S.r[row * KG + k] : 0.0;
+    }
+    __syncthreads();
+    double un[KG], xn[KG];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      un[k] = sv[0][k] * sv[0][k] + sv[1][k] * sv[1][k];
+      xn[k] = xv[0][k] * xv[0][k] + xv[1][k] * xv[1][k];
+    }
+    wg_sum<KG>(rr, S.red);
+    wg_sum<KG>(un, S.red);
+    wg_sum<KG>(xn, S.red);
+    double worst = 0.0;
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      if (k < kn) {
+        const double den = anorm * (anorm * sqrt(xn[k]) + sqrt(rr[k]));
+        const double be = den > 0.0 ? sqrt(un[k]) / den : 0.0;
+        worst = (be > worst || be != be) ? be : worst;
+      }
+    }
+    if (worst <= kRefineTol) {
+      store_rows<KG>(t.B, t.ldb, n, k0, t.nrhs, xv);
+      if (t.X) store_rows<KG>(t.X, t.n, n, k0, t.nrhs, xv);
+      return it;
+    }
+    // Give up at the cap, or when four iterations have not halved the error.
+    if (it >= kRefineMaxIt || !(worst == worst) || (it >= 4 && worst > 0.5 * h4)) return -1;
+    h4 = h3;
+    h3 = h2;
+    h2 = h1;
+    h1 = worst;
+    // s = R^-T u, p = s + (gamma' / gamma) p
+    fwdsub_t<KG>(t, sv, S.z);
+    double g2[KG];
+#pragma unroll
+    for (int k = 0; k < KG; ++k) g2[k] = sv[0][k] * sv[0][k] + sv[1][k] * sv[1][k];
+    wg_sum<KG>(g2, S.red);
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      const double be = (it == 0 || gam[k] == 0.0) ? 0.0 : g2[k] / gam[k];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) pv[h][k] = sv[h][k] + be * (it == 0 ? 0.0 : pv[h][k]);
+      gam[k] = g2[k];
+    }
+    // t = R^-1 p (in sv), alpha = gamma / ||A t||^2, x += alpha t
+#pragma unroll
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+      for (int k = 0; k < KG; ++k) sv[h][k] = pv[h][k];
+    backsub<KG>(t, sv, S.z);
+    put_vector(t, sv, S.v);
+    __syncthreads();
+    double qq[KG] = {};
+    for (int r0 = 0; r0 < m; r0 += NT) {
+      const int i = r0 + l;
+      if (i < m) {
+        double acc[KG] = {};
+        for (int j = 0; j < n; ++j) {
+          const double a = A[(int64_t)j * t.lda + i];
+#pragma unroll
+          for (int k = 0; k < KG; ++k) acc[k] += a * S.v[j * KG + k];
+        }
+#pragma unroll
+        for (int k = 0; k < KG; ++k) qq[k] += acc[k] * acc[k];
+      }
+    }
+    __syncthreads();
+    wg_sum<KG>(qq, S.red);
+#pragma unroll
+    for (int k = 0; k < KG; ++k) {
+      const double al = qq[k] > 0.0 ? gam[k] / qq[k] : 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) xv[h][k] += al * sv[h][k];
+    }
+  }
+}
+
+// Copy R into A's upper triangle (kTaskWriteR).
+__device__ void write_r(const BatchTask& t) {
+  for (int c = 0; c < t.n; ++c)
+    for (int j = threadIdx.x; j <= c; j += NT)
+      gp(t.A)[j + (int64_t)c * t.lda] = gp(t.R)[j + (int64_t)c * t.n];
+}
+
+// Register budgets (waves per SIMD, hence workgroups per CU): 256 VGPRs for
+// the FP64 tiles of three or five slots, 168 for two and for five FP32
+// slots, 128 for two or three FP32 slots.
+template <int P, int MAXT>
+struct Budget {
+  static constexpr int waves = P == kBlkF64 ? (MAXT >= 3 ? 2 : 3) : (MAXT >= 5 ? 3 : 4);
+};
+
+// The sweep of one queue's problems.  FP64 finishes each problem (status,
+// X, R into A); the mixed precisions leave R and C for k_batched_refine.
+template <int P, int MAXT>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(Budget<P, MAXT>::waves)))
+void k_batched_blk(const BatchHeader* table, int queue, int* counter, int* status) {
+  using W = typename Prec<P>::W;
+  __shared__ __align__(16) BlkLds<W> S;
+  const int total = __builtin_amdgcn_readfirstlane(table->count[queue]);
+  const int base = __builtin_amdgcn_readfirstlane(table->begin[queue]);
+  const BatchTask* tasks = (const BatchTask*)(table + 1) + base;
+  for (;;) {
+    if (threadIdx.x == 0) S.idx = atomicAdd(counter + queue, 1);
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(S.idx);
+    __syncthreads();
+    if (idx >= total) break;
+    const BatchTask t = tasks[idx];
+    sweep<P, MAXT>(t, S);
+    if constexpr (P == kBlkF64) {
+      const int st = finish_f64(t, S);
+      if (st == 0 && (t.flags & kTaskWriteR)) write_r(t);
+      if (threadIdx.x == 0) status[t.slot] = st;
+    }
+    __syncthreads();
+  }
+}
+
+// FP64 refinement of the mixed-precision solves of queues 1 .. 3 (one
+// problem per workgroup, popped from queue counter kBatchQueues).
+__global__ __launch_bounds__(NT) void k_batched_refine(const BatchHeader* table, int* counter,
+                                                       int* status, int* iters) {
+  __shared__ __align__(16) RefineLds S;
+  int total = 0;
+  for (int k = 1; k < kBatchQueues; ++k) total += table->count[k];
+  total = __builtin_amdgcn_readfirstlane(total);
+  const int base = __builtin_amdgcn_readfirstlane(table->begin[1]);
+  const BatchTask* tasks = (const BatchTask*)(table + 1) + base;
+  for (;;) {
+    if (threadIdx.x == 0) S.idx = atomicAdd(counter + kBatchQueues, 1);
+    __syncthreads();
+    const int idx = __builtin_amdgcn_readfirstlane(S.idx);
+    __syncthreads();
+    if (idx >= total) break;
+    const BatchTask t = tasks[idx];
+    // ||A||_F
+    double an[1] = {0.0};
+    for (int c = 0; c < t.n; ++c) {
+      const gdouble* ac = gp(t.A) + (int64_t)c * t.lda;
+      for (int i = threadIdx.x; i < t.m; i += NT) an[0] += ac[i] * ac[i];
+    }
+    wg_sum<1>(an, S.red);
+    const double anorm = sqrt(an[0]);
+    int st = zero_diagonal(t, &S.sing) == INT_MAX ? 0 : kStatusNoConv;
+    int most = 0;
+    for (int k0 = 0; st == 0 && k0 < t.nrhs; k0 += KG) {
+      const int it = refine_group(t, S, anorm, k0);
+      if (it < 0)
+        st = kStatusNoConv;
+      else
+        most = max(most, it);
+    }
+    if (st == 0 && (t.flags & kTaskWriteR)) write_r(t);
+    if (threadIdx.x == 0) {
+      status[t.slot] = st;
+      if (iters) iters[t.slot] = st == 0 ? most : -1;
+    }
+    __syncthreads();
+  }
+}
+
+constexpr int kTiles[kBatchQueues] = {0, 2, 3, 5};
+
+template <int P>
+const void* blk_kernel(int queue) {
+  switch (queue) {
+    case 1:
+      return (const void*)k_batched_blk<P, 2>;
+    case 2:
+      return (const void*)k_batched_blk<P, 3>;
+    default:
+      return (const void*)k_batched_blk<P, 5>;
+  }
+}
+
+const void* blk_kernel(int prec, int queue) {
+  if (prec == kBlkF32) return blk_kernel<kBlkF32>(queue);
+  if (prec == kBlkBF16) return blk_kernel<kBlkBF16>(queue);
+  return blk_kernel<kBlkF64>(queue);
+}
+
+int occupancy_grid(int device, const void* k) {
+  int cus = 256;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    cus = 256;
+  int per = 1;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k, NT, 0) != hipSuccess || per < 1) per = 1;
+  return cus * per;
+}
+
+}  // namespace
+
+int batch_queue(const BatchTask& t) {
+  if (t.flags & kTaskApply) return 0;
+  const int tiles = (t.n + t.nrhs + 15) / 16;
+  for (int k = 1; k < kBatchQueues; ++k)
+    if (tiles <= NW * kTiles[k]) return k;
+  return kBatchQueues - 1;
+}
+
+int batched_blk_grid(int device, int prec, int queue) {
+  return occupancy_grid(device, queue == kBatchQueues ? (const void*)k_batched_refine
+                                                      : blk_kernel(prec, queue));
+}
+
+void batched_blk_launch(hipStream_t s, const BatchHeader* table, int queue, int* counter,
+                        int* status, int* iters, int grid, int prec) {
+  if (grid <= 0) return;
+  if (queue == kBatchQueues) {
+    hipLaunchKernelGGL(k_batched_refine, dim3(grid), dim3(NT), 0, s, table, counter, status, iters);
+    return;
+  }
+  const void* k = blk_kernel(prec, queue);
+  void* args[] = {(void*)&table, (void*)&queue, (void*)&counter, (void*)&status};
+  (void)hipLaunchKernel(k, dim3(grid), dim3(NT), args, 0, s);
+}
+
+}  // namespace miqr

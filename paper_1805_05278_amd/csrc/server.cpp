@@ -97,9 +97,10 @@ struct Req {
   int64_t lda = 0, ldb = 0, ldx = 0;
   int64_t parent = -1;  // factored request whose kept factors this one reuses
   bool keep = false;    // keep A (reflector blocks), R and tau after completion
+  bool redo = false;    // mixed-precision refinement missed its target: solve in FP64
   State state = PENDING;
   Buf A, B, R, C, tau;
-  int ev = -1;          // upload event slot
+  int ev = -1;          // upload event slot (-1: nothing to wait for)
   int64_t xoff = 0;     // offset (doubles) of its solution in the batch staging
   int status = 0;
   int batch_size = 0;
@@ -134,7 +135,9 @@ struct miqr_server {
   Slot slots[2];
   std::vector<hipEvent_t> up_events;
   std::vector<int> up_refs;  // requests still to be launched after each upload event
-  int grid = 1;
+  int prec = kBlkF64;     // working precision of the batches
+  BatchGrids grids{};     // persistent grids for that precision
+  BatchGrids grids64{};   // and for FP64 re-solves
   int64_t next_id = 1;
   std::unordered_map<int64_t, Req> reqs;
   std::deque<int64_t> pending;
@@ -244,14 +247,21 @@ miqr_status admit(miqr_server* s) {
   return MIQR_OK;
 }
 
+// Launch the next batch on slot sl.  A batch is either requests in the
+// server's precision (one replay of the slot's graph) or FP64 re-solves of
+// mixed-precision requests whose refinement missed its target (the same
+// sequence launched directly).  Tasks are grouped by queue of the batched
+// kernels, largest first within a queue.
 miqr_status launch(miqr_server* s, Slot& sl) {
-  BatchTask* tasks = batch_tasks(sl.ptable);
+  const bool redo = s->reqs[s->admitted.front()].redo;
   int count = 0;
   int64_t xoff = 0;
   std::vector<int> evs;
+  std::vector<BatchTask> tk;
   sl.ids.clear();
   while (!s->admitted.empty() && count < s->max_batch) {
     Req& r = s->reqs[s->admitted.front()];
+    if (r.redo != redo) break;
     const int64_t xs = r.n * r.nrhs;
     if (xoff + xs > (int64_t)s->stage_doubles) break;
     BatchTask t{};
@@ -275,23 +285,61 @@ miqr_status launch(miqr_server* s, Slot& sl) {
     t.m = (int)r.m;
     t.n = (int)r.n;
     t.nrhs = (int)r.nrhs;
-    t.slot = count;
-    tasks[count++] = t;
+    t.slot = count++;
+    tk.push_back(t);
     r.xoff = xoff;
     xoff += (xs + 31) & ~int64_t(31);
     r.state = RUNNING;
-    if (std::find(evs.begin(), evs.end(), r.ev) == evs.end()) evs.push_back(r.ev);
+    if (r.ev >= 0 && std::find(evs.begin(), evs.end(), r.ev) == evs.end()) evs.push_back(r.ev);
     sl.ids.push_back(r.id);
     s->admitted.pop_front();
   }
   if (count == 0) return MIQR_OK;
-  sl.ptable->count = count;
+  std::vector<int> q(tk.size());
+  std::vector<size_t> order(tk.size());
+  for (size_t k = 0; k < tk.size(); ++k) {
+    q[k] = batch_queue(tk[k]);
+    order[k] = k;
+  }
+  auto cost = [&](size_t k) {
+    const double N = (double)tk[k].n + tk[k].nrhs;
+    return ((tk[k].m + kBatchRows - 1) / kBatchRows + 1) * N * N;
+  };
+  std::stable_sort(order.begin(), order.end(), [&](size_t a, size_t b) {
+    return q[a] != q[b] ? q[a] < q[b] : cost(a) > cost(b);
+  });
+  BatchHeader* hd = sl.ptable;
+  *hd = BatchHeader{};
+  hd->total = count;
+  BatchTask* tasks = batch_tasks(hd);
+  for (size_t k = 0; k < order.size(); ++k) {
+    tasks[k] = tk[order[k]];
+    hd->count[q[order[k]]]++;
+  }
+  for (int k = 1; k < kBatchQueues; ++k) hd->begin[k] = hd->begin[k - 1] + hd->count[k - 1];
   hipError_t e = hipSuccess;
   for (int ev : evs) {
     if (e == hipSuccess) e = hipStreamWaitEvent(s->compute, s->up_events[ev], 0);
   }
-  for (int64_t id : sl.ids) s->up_refs[s->reqs[id].ev]--;
-  if (e == hipSuccess) e = hipGraphLaunch(sl.exec, s->compute);
+  for (int64_t id : sl.ids) {
+    Req& r = s->reqs[id];
+    if (r.ev >= 0) s->up_refs[r.ev]--;
+    r.ev = -1;
+  }
+  if (!redo) {
+    if (e == hipSuccess) e = hipGraphLaunch(sl.exec, s->compute);
+  } else {
+    const size_t tb = batch_table_bytes(count);
+    if (e == hipSuccess) e = hipMemcpyAsync(sl.dtable, sl.ptable, tb, hipMemcpyHostToDevice, s->compute);
+    if (e == hipSuccess) {
+      batched_ls(s->compute, sl.dtable, sl.dcounter, sl.dstatus, nullptr, s->grids64, kBlkF64, 0.0,
+                 0.0);
+      e = hipGetLastError();
+    }
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(sl.pstatus, sl.dstatus, (size_t)count * 4, hipMemcpyDeviceToHost,
+                         s->compute);
+  }
   if (e == hipSuccess)
     e = hipMemcpyAsync(sl.px, sl.dx, (size_t)xoff * 8, hipMemcpyDeviceToHost, s->compute);
   if (e == hipSuccess) e = hipEventRecord(sl.done, s->compute);
@@ -299,7 +347,7 @@ miqr_status launch(miqr_server* s, Slot& sl) {
   const double t = s->now();
   for (int64_t id : sl.ids) {
     Req& r = s->reqs[id];
-    r.t_start = t;
+    if (!r.redo) r.t_start = t;
     r.batch_size = count;
   }
   sl.busy = true;
@@ -308,10 +356,18 @@ miqr_status launch(miqr_server* s, Slot& sl) {
 
 void retire(miqr_server* s, Slot& sl) {
   const double t = s->now();
+  std::vector<int64_t> again;
   for (size_t k = 0; k < sl.ids.size(); ++k) {
     const int64_t id = sl.ids[k];
     Req& r = s->reqs[id];
     r.status = sl.pstatus[k];
+    if (r.status == kStatusNoConv) {
+      // A and B are on the device as uploaded: solve again in FP64.
+      r.redo = true;
+      r.state = ADMITTED;
+      again.push_back(id);
+      continue;
+    }
     const double* src = sl.px + r.xoff;
     for (int64_t k = 0; k < r.nrhs; ++k)
       std::memcpy(r.hX + k * r.ldx, src + k * r.n, (size_t)r.n * 8);
@@ -334,6 +390,7 @@ void retire(miqr_server* s, Slot& sl) {
     s->finished.push_back(d);
     if (!r.keep) s->reqs.erase(id);
   }
+  for (auto it = again.rbegin(); it != again.rend(); ++it) s->admitted.push_front(*it);
   sl.ids.clear();
   sl.busy = false;
 }
@@ -373,7 +430,8 @@ miqr_status make_slot(miqr_server* s, Slot& sl) {
   e = hipStreamBeginCapture(s->compute, hipStreamCaptureModeRelaxed);
   if (e == hipSuccess) e = hipMemcpyAsync(sl.dtable, sl.ptable, tb, hipMemcpyHostToDevice, s->compute);
   if (e == hipSuccess) {
-    batched_ls(s->compute, sl.dtable, sl.dcounter, sl.dstatus, s->grid, 0.0, 0.0);
+    batched_ls(s->compute, sl.dtable, sl.dcounter, sl.dstatus, nullptr, s->grids, s->prec, 0.0,
+               0.0);
     e = hipGetLastError();
   }
   if (e == hipSuccess)
@@ -433,6 +491,17 @@ miqr_status qr_server_create(miqr_handle h, const qr_server_opts* o, miqr_server
     h->err = "stage_bytes too small for one request";
     return MIQR_EINVAL;
   }
+  const int prec = o ? o->precision : MIQR_FP64;
+  if (prec != MIQR_FP64 && prec != MIQR_MIXED_FP32 && prec != MIQR_MIXED_BF16) {
+    h->err = "unknown precision";
+    return MIQR_EINVAL;
+  }
+  if (prec != MIQR_FP64 && o->keep_factors) {
+    // Kept factors are replayed on later right-hand sides without
+    // refinement, so they are FP64 only.
+    h->err = "keep_factors needs precision MIQR_FP64";
+    return MIQR_ENOTSUP;
+  }
   if (hipSetDevice(h->device) != hipSuccess) return MIQR_EHIP;
   miqr_server* s = new miqr_server();
   s->h = h;
@@ -441,7 +510,9 @@ miqr_status qr_server_create(miqr_handle h, const qr_server_opts* o, miqr_server
   s->stage_doubles = (size_t)stage / 8;
   s->keep = o && o->keep_factors;
   s->t0 = std::chrono::steady_clock::now();
-  s->grid = batched_grid(h->device, (int)maxb);
+  s->prec = prec == MIQR_MIXED_FP32 ? kBlkF32 : (prec == MIQR_MIXED_BF16 ? kBlkBF16 : kBlkF64);
+  s->grids = batched_grids(h->device, s->prec);
+  s->grids64 = batched_grids(h->device, kBlkF64);
   hipError_t e = hipStreamCreateWithFlags(&s->compute, hipStreamNonBlocking);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->copy, hipStreamNonBlocking);
   if (e != hipSuccess) {

@@ -26,9 +26,15 @@ def miqr():
 
 
 # Edge shapes: square, one block exactly, ragged tail, single column, fewer
-# rows than a block, the widest n + nrhs, eight right-hand sides.
+# rows than a block, the widest n + nrhs, eight right-hand sides; panels of
+# sixteen columns full, partial, and with right-hand sides in the panel's
+# tile or in a tile of their own; n + nrhs at each queue boundary (128 / 129,
+# 192 / 193, 256 / 257 columns) and at the limit of 320.
 EDGE = [(256, 256, 1), (64, 64, 2), (65, 7, 1), (1000, 1, 1), (10, 5, 3), (129, 128, 4),
-        (4096, 256, 4), (700, 312, 8), (64, 8, 1), (4095, 255, 2)]
+        (4096, 256, 4), (700, 312, 8), (64, 8, 1), (4095, 255, 2),
+        (16, 16, 1), (17, 17, 3), (300, 15, 1), (300, 16, 1), (333, 31, 2), (1500, 124, 4),
+        (1500, 125, 4), (900, 188, 4), (900, 189, 4), (2000, 253, 3), (2000, 253, 4),
+        (520, 312, 8), (3000, 64, 8)]
 
 
 def trace_shapes(k, seed):
@@ -136,7 +142,10 @@ def test_batched_argument_errors(miqr):
     A = m_.colmajor(100, 10)
     B = m_.colmajor(100, 1)
     with pytest.raises(m_.MiqrError) as e:
-        h.lstsq_batched([A], [B], h.opts(precision=m_.MIXED_FP32))
+        h.lstsq_batched([A], [B], h.opts(precision=7))
+    assert e.value.status == m_.EINVAL
+    with pytest.raises(m_.MiqrError) as e:
+        h.lstsq_batched([A], [B], h.opts(normalize=1))
     assert e.value.status == m_.ENOTSUP
     assert h.lstsq_batched([], []) == (m_.OK, [])
 

@@ -188,3 +188,37 @@ def test_server_errors_and_singular(miqr):
     with pytest.raises(m_.MiqrError):
         srv.resolve(r2, B2, x3)  # not kept
     srv.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_server_mixed_precision_matches_batched(miqr, prec):
+    """A mixed-precision server: every result bitwise equal to the same problem
+    solved alone by the mixed batched call, and within the FP64 backward-error
+    gate; a request too ill-conditioned for the products is solved again in
+    FP64 in a later batch, bitwise equal to the FP64 call."""
+    m_, h = miqr
+    p = {"fp32": m_.MIXED_FP32, "bf16": m_.MIXED_BF16}[prec]
+    sh = shapes(24, 57)
+    probs = problems(sh, 7600)
+    A1 = np.asfortranarray(synth.conditioned(1200, 100, 1e12, 7701))
+    _, B1 = synth.ls_rhs(A1, 7702, noise=1e-6, nrhs=2)
+    probs.append((A1, np.asfortranarray(B1)))
+    X = [np.zeros((A.shape[1], B.shape[1]), order="F") for A, B in probs]
+    srv = m_.Server(h, hbm_budget=256 << 20, max_batch=8, precision=p)
+    ids = [srv.submit(A, B, x) for (A, B), x in zip(probs, X)]
+    done = drain(srv, ids)
+    srv.close()
+    for i, rid in enumerate(ids):
+        assert done[rid]["status"] == 0
+        A, B = probs[i]
+        Ad, Bd = m_.to_colmajor(A), m_.to_colmajor(B)
+        last = i == len(probs) - 1
+        st, stat, its = h.lstsq_batched([Ad], [Bd], h.opts(precision=p), want_iters=True)
+        torch.cuda.synchronize()
+        assert stat == [0] and (its[0] == -1) == last
+        assert np.array_equal(X[i], Bd.cpu().numpy()[: A.shape[1]]), i
+        for c in range(B.shape[1]):
+            assert oracle.backward_error(A, X[i][:, c], B[:, c]) <= 1e-13
+    with pytest.raises(m_.MiqrError) as e:
+        m_.Server(h, keep_factors=True, precision=p)
+    assert e.value.status == m_.ENOTSUP
