@@ -158,6 +158,14 @@ __device__ __forceinline__ double readlane(double v, int lane) {
 // from it are then computed where they are used.  Otherwise the compiler
 // hoists them out of the sweep's loops as invariants and holds dozens of
 // them in registers for the whole problem, spilling the tiles.
+// Workgroup barrier that orders LDS only: global loads in flight (a
+// prefetch) stay in flight across it.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 __device__ __forceinline__ int lane_id() {
   int l = threadIdx.x & 63;
   asm volatile("" : "+v"(l));
@@ -179,9 +187,12 @@ struct BlkLds {
   double z[2][8];
   int idx, sing;
 };
+constexpr int RC = 16;  // rows of A per chunk of a refinement pass
 struct RefineLds {
-  double v[kBatchMaxCols * KG];  // a vector of length n per right-hand side, [row][rhs]
-  double r[kBatchMaxCols * KG];  // a row chunk of the residual, then A^T r, [row][rhs]
+  double v[kBatchMaxCols * KG];      // a vector of length n per right-hand side, [row][rhs]
+  double a[kBatchMaxCols * RC];      // the chunk's entries of A, [column][row]
+  double part[NT / RC][RC][KG];      // per-group partial sums of A v, [group][row][rhs]
+  double rc[RC][KG];                 // the chunk's residual
   double red[NW][KG];
   double z[2][8];
   int idx, sing;
@@ -280,8 +291,13 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
     if (sig2 != 0.0) {
       const double nrm = sqrt(alpha * alpha + sig2);
       beta = alpha >= 0.0 ? -nrm : nrm;
-      tau = (beta - alpha) / beta;
-      sc = 1.0 / (alpha - beta);
+      // tau = (beta - alpha) / beta and sc = 1 / (alpha - beta) from one
+      // division: with d = alpha - beta and g = 1 / (beta d), sc = beta g and
+      // tau = -d^2 g.
+      const double d = alpha - beta;
+      const double g = 1.0 / (beta * d);
+      sc = beta * g;
+      tau = -d * d * g;
     }
     if (cl == jj) {
 #pragma unroll
@@ -503,78 +519,81 @@ __device__ __forceinline__ void wg_sum(double (&v)[KK], double (*red)[KG]) {
   __syncthreads();
 }
 
+// One step of a triangular solve by rows: the owner of row i divides by the
+// diagonal entry and posts z_i; after the barrier every row `act` subtracts
+// its entry times z_i.  a0 / a1: this thread's entries (rows l, l + NT) of
+// the column (or row) of R that step i uses.
+template <int KK>
+__device__ __forceinline__ void solve_step(int i, double a0, double a1, bool act0, bool act1,
+                                           double (&v)[2][KK], double (*zb)[8]) {
+  const int l = threadIdx.x, s = i & 1;
+  if (l == i)
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+      v[0][k] = v[0][k] / a0;
+      zb[s][k] = v[0][k];
+    }
+  if (l + NT == i)
+#pragma unroll
+    for (int k = 0; k < KK; ++k) {
+      v[1][k] = v[1][k] / a1;
+      zb[s][k] = v[1][k];
+    }
+  __syncthreads();
+  if (act0)
+#pragma unroll
+    for (int k = 0; k < KK; ++k) v[0][k] -= a0 * zb[s][k];
+  if (act1)
+#pragma unroll
+    for (int k = 0; k < KK; ++k) v[1][k] -= a1 * zb[s][k];
+}
+
+constexpr int SB = 16;  // steps of a triangular solve whose entries of R load together
+
 // R z = v in place by back substitution (R upper triangular, n x n in t.R);
 // thread l holds rows l and l + NT of KK right-hand sides.  One barrier per
-// row; the next column of R is loaded during the current step.
+// row; the entries of R for SB columns are loaded in one go, so the steps do
+// not wait on memory.
 template <int KK>
 __device__ void backsub(const BatchTask& t, double (&v)[2][KK], double (*zb)[8]) {
   const int l = threadIdx.x, n = t.n, l1 = l + NT;
   const gdouble* R = gp(t.R);
-  double c0 = (l < n) ? R[(int64_t)(n - 1) * n + l] : 0.0;
-  double c1 = (l1 < n) ? R[(int64_t)(n - 1) * n + l1] : 0.0;
-  for (int i = n - 1; i >= 0; --i) {
-    const int s = i & 1;
-    const double a0 = c0, a1 = c1;  // R[l][i], R[l1][i]
-    if (i >= 1) {
-      c0 = (l < i) ? R[(int64_t)(i - 1) * n + l] : 0.0;
-      c1 = (l1 < i) ? R[(int64_t)(i - 1) * n + l1] : 0.0;
+  for (int top = n - 1; top >= 0; top -= SB) {
+    double c0[SB], c1[SB];  // R[l][top - u], R[l1][top - u]
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int col = top - u;
+      c0[u] = (col >= 0 && l <= col) ? R[(int64_t)col * n + l] : 0.0;
+      c1[u] = (col >= 0 && l1 <= col) ? R[(int64_t)col * n + l1] : 0.0;
     }
-    if (l == i)
 #pragma unroll
-      for (int k = 0; k < KK; ++k) {
-        v[0][k] = v[0][k] / a0;
-        zb[s][k] = v[0][k];
-      }
-    if (l1 == i)
-#pragma unroll
-      for (int k = 0; k < KK; ++k) {
-        v[1][k] = v[1][k] / a1;
-        zb[s][k] = v[1][k];
-      }
-    __syncthreads();
-    if (l < i)
-#pragma unroll
-      for (int k = 0; k < KK; ++k) v[0][k] -= a0 * zb[s][k];
-    if (l1 < i)
-#pragma unroll
-      for (int k = 0; k < KK; ++k) v[1][k] -= a1 * zb[s][k];
+    for (int u = 0; u < SB; ++u) {
+      const int i = top - u;
+      if (i >= 0) solve_step<KK>(i, c0[u], c1[u], l < i, l1 < i, v, zb);
+    }
   }
   __syncthreads();
 }
 
-// R^T z = v in place by forward substitution (row i of R enters step i).
+// R^T z = v in place by forward substitution (row i of R enters step i;
+// R^T is lower triangular).  Entries of SB rows of R load together.
 template <int KK>
 __device__ void fwdsub_t(const BatchTask& t, double (&v)[2][KK], double (*zb)[8]) {
   const int l = threadIdx.x, n = t.n, l1 = l + NT;
   const gdouble* R = gp(t.R);
-  double c0 = (l < n) ? R[(int64_t)l * n] : 0.0;
-  double c1 = (l1 < n) ? R[(int64_t)l1 * n] : 0.0;
-  for (int i = 0; i < n; ++i) {
-    const int s = i & 1;
-    const double a0 = c0, a1 = c1;  // R[i][l], R[i][l1]
-    if (i + 1 < n) {
-      c0 = (l > i && l < n) ? R[(int64_t)l * n + i + 1] : 0.0;
-      c1 = (l1 > i && l1 < n) ? R[(int64_t)l1 * n + i + 1] : 0.0;
+  for (int i0 = 0; i0 < n; i0 += SB) {
+    double c0[SB], c1[SB];  // R[i0 + u][l], R[i0 + u][l1]
+#pragma unroll
+    for (int u = 0; u < SB; ++u) {
+      const int i = i0 + u;
+      c0[u] = (i < n && l >= i && l < n) ? R[(int64_t)l * n + i] : 0.0;
+      c1[u] = (i < n && l1 >= i && l1 < n) ? R[(int64_t)l1 * n + i] : 0.0;
     }
-    if (l == i)
 #pragma unroll
-      for (int k = 0; k < KK; ++k) {
-        v[0][k] = v[0][k] / a0;
-        zb[s][k] = v[0][k];
-      }
-    if (l1 == i)
-#pragma unroll
-      for (int k = 0; k < KK; ++k) {
-        v[1][k] = v[1][k] / a1;
-        zb[s][k] = v[1][k];
-      }
-    __syncthreads();
-    if (l > i && l < n)
-#pragma unroll
-      for (int k = 0; k < KK; ++k) v[0][k] -= a0 * zb[s][k];
-    if (l1 > i && l1 < n)
-#pragma unroll
-      for (int k = 0; k < KK; ++k) v[1][k] -= a1 * zb[s][k];
+    for (int u = 0; u < SB; ++u) {
+      const int i = i0 + u;
+      if (i < n) solve_step<KK>(i, c0[u], c1[u], l > i && l < n, l1 > i && l1 < n, v, zb);
+    }
   }
   __syncthreads();
 }
@@ -621,12 +640,12 @@ __device__ __forceinline__ void store_rows(double* M, int64_t ld, int n, int k0,
 // R_jj == 0, B's top rows receive c and the status is j + 1.
 __device__ int finish_f64(const BatchTask& t, BlkLds<double>& S) {
   const int sing = zero_diagonal(t, &S.sing);
-  for (int k0 = 0; k0 < t.nrhs; k0 += 8) {
-    double v[2][8];
-    load_rows<8>(t.C, t.n, t.n, k0, t.nrhs, v);
-    if (sing == INT_MAX) backsub<8>(t, v, S.z);
-    store_rows<8>(t.B, t.ldb, t.n, k0, t.nrhs, v);
-    if (t.X) store_rows<8>(t.X, t.n, t.n, k0, t.nrhs, v);
+  for (int k0 = 0; k0 < t.nrhs; k0 += KG) {
+    double v[2][KG];
+    load_rows<KG>(t.C, t.n, t.n, k0, t.nrhs, v);
+    if (sing == INT_MAX) backsub<KG>(t, v, S.z);
+    store_rows<KG>(t.B, t.ldb, t.n, k0, t.nrhs, v);
+    if (t.X) store_rows<KG>(t.X, t.n, t.n, k0, t.nrhs, v);
   }
   return sing == INT_MAX ? 0 : sing + 1;
 }
@@ -643,84 +662,115 @@ __device__ __forceinline__ void put_vector(const BatchTask& t, const double (&v)
   }
 }
 
-// Column tiles per wave for A^T r (n <= kBatchMaxCols).
-constexpr int RT = (kBatchMaxCols + 16 * NW - 1) / (16 * NW);
+// One pass over A in chunks of RC rows, v (n x KG) in S.v.  Thread (ri, g) =
+// (l % RC, l / RC) forms row ri's partial sums of A v over the columns
+// j = g mod (NT / RC), keeping the entries in LDS; the partials are summed
+// over g.  RESID: the chunk's residual r = b - A v, then u += A^T r from the
+// LDS copy (thread l: columns l and l + NT, the row layout of the solves),
+// rr += ||r||^2 and a2 += ||A||_F^2; otherwise rr += ||A v||^2.
+template <bool RESID>
+__device__ void a_pass(const BatchTask& t, int k0, int kn, RefineLds& S, double (&rr)[KG],
+                       double (&u)[2][KG], double& a2) {
+  constexpr int G = NT / RC;                          // column groups
+  constexpr int PJ = (kBatchMaxCols + G - 1) / G;     // columns per thread
+  const int l = threadIdx.x, ri = l % RC, g = l / RC;
+  const int m = t.m, n = t.n;
+  const gdouble* A = gp(t.A);
+  const gdouble* B = gp(t.B);
+  // The next chunk's entries are loaded while the current chunk is reduced
+  // (the barriers below order LDS only, so the loads stay in flight).
+  double pre[PJ];
+  auto fetch = [&](int r0) {
+    // The column group through an empty asm: the 20 column offsets are
+    // formed here rather than hoisted out of the loop and held.
+    int gg = g;
+    asm volatile("" : "+v"(gg));
+    const int i = r0 + ri;
+    const gdouble* ai = A + (i < m ? i : 0) + (int64_t)gg * t.lda;
+    const int64_t step = (int64_t)G * t.lda;
+#pragma unroll
+    for (int s = 0; s < PJ; ++s) pre[s] = (i < m && gg + G * s < n) ? ai[s * step] : 0.0;
+  };
+  fetch(0);
+  for (int r0 = 0; r0 < m; r0 += RC) {
+    double acc[KG] = {};
+#pragma unroll
+    for (int s = 0; s < PJ; ++s) {
+      const int j = g + G * s;
+      if (j < n) {
+        const double a = pre[s];
+        if (RESID) {
+          S.a[j * RC + ri] = a;
+          a2 += a * a;
+        }
+#pragma unroll
+        for (int k = 0; k < KG; ++k) acc[k] += a * S.v[j * KG + k];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KG; ++k) S.part[g][ri][k] = acc[k];
+    if (r0 + RC < m) fetch(r0 + RC);
+    lds_barrier();
+    if (l < RC * KG) {
+      // Row l % RC, right-hand side l / RC: the partials in group order.
+      const int rr_ = l % RC, k = l / RC;
+      double sum = 0.0;
+#pragma unroll
+      for (int gg = 0; gg < G; ++gg) sum += S.part[gg][rr_][k];
+      const int row = r0 + rr_;
+      double v = sum;
+      if (RESID) v = (row < m && k < kn) ? B[(int64_t)(k0 + k) * t.ldb + row] - sum : 0.0;
+      S.rc[rr_][k] = v;
+    }
+    lds_barrier();
+    if (l < RC) {
+#pragma unroll
+      for (int k = 0; k < KG; ++k) rr[k] += S.rc[l][k] * S.rc[l][k];
+    }
+    if (RESID) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int col = l + h * NT;
+        if (col < n) {
+#pragma unroll
+          for (int q = 0; q < RC; ++q) {
+            const double a = S.a[col * RC + q];
+#pragma unroll
+            for (int k = 0; k < KG; ++k) u[h][k] += a * S.rc[q][k];
+          }
+        }
+      }
+    }
+    lds_barrier();
+  }
+}
 
 // FP64 refinement of right-hand sides k0 .. k0 + KG - 1 (see the file
 // comment).  Returns the iterations used, or -1 if the target was not met.
-__device__ int refine_group(const BatchTask& t, RefineLds& S, double anorm, int k0) {
-  const int l = threadIdx.x, w = l >> 6;
-  const int m = t.m, n = t.n;
+// *anorm: ||A||_F, taken from the first residual pass when zero.
+__device__ int refine_group(const BatchTask& t, RefineLds& S, double* anorm, int k0) {
+  const int n = t.n;
   const int kn = min(KG, t.nrhs - k0);
-  const gdouble* A = gp(t.A);
-  const gdouble* B = gp(t.B);
   double xv[2][KG], pv[2][KG], sv[2][KG];
   load_rows<KG>(t.C, t.n, n, k0, t.nrhs, xv);
   backsub<KG>(t, xv, S.z);
   double gam[KG] = {};
   double h1 = 0.0, h2 = 0.0, h3 = 0.0, h4 = 0.0;  // worst of the last four iterations
   for (int it = 0;; ++it) {
-    // r = b - A x row by row; u = A^T r from the same chunk (lane (q, cl)
-    // sums column 16 c + cl over the chunk rows = q mod 4).
+    // r = b - A x and u = A^T r in one pass over A.
     put_vector(t, xv, S.v);
     __syncthreads();
     double rr[KG] = {};
-    double u[RT][KG] = {};
-    for (int r0 = 0; r0 < m; r0 += NT) {
-      const int i = r0 + l;
-      double acc[KG] = {};
-      if (i < m) {
-        for (int j = 0; j < n; ++j) {
-          const double a = A[(int64_t)j * t.lda + i];
+    double a2[1] = {0.0};
 #pragma unroll
-          for (int k = 0; k < KG; ++k) acc[k] += a * S.v[j * KG + k];
-        }
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int k = 0; k < KG; ++k)
-          acc[k] = (k < kn ? B[(int64_t)(k0 + k) * t.ldb + i] : 0.0) - acc[k];
-      }
-#pragma unroll
-      for (int k = 0; k < KG; ++k) {
-        S.r[l * KG + k] = acc[k];
-        rr[k] += acc[k] * acc[k];
-      }
-      __syncthreads();
-      const int rows = min(NT, m - r0);
-      const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
-#pragma unroll
-      for (int ii = 0; ii < RT; ++ii) {
-        const int col = 16 * (w + NW * ii) + cl;
-        if (col < n) {
-          const gdouble* ac = A + (int64_t)col * t.lda + r0;
-          for (int s = q; s < rows; s += 4) {
-            const double a = ac[s];
-#pragma unroll
-            for (int k = 0; k < KG; ++k) u[ii][k] += a * S.r[s * KG + k];
-          }
-        }
-      }
-      __syncthreads();
+      for (int k = 0; k < KG; ++k) sv[h][k] = 0.0;
+    a_pass<true>(t, k0, kn, S, rr, sv, a2[0]);
+    if (*anorm == 0.0) {
+      wg_sum<1>(a2, S.red);
+      *anorm = sqrt(a2[0]);
     }
-    {
-      const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
-#pragma unroll
-      for (int ii = 0; ii < RT; ++ii) {
-        const int col = 16 * (w + NW * ii) + cl;
-#pragma unroll
-        for (int k = 0; k < KG; ++k) {
-          const double s = rows_sum(u[ii][k]);
-          if (q == 0 && col < n) S.r[col * KG + k] = s;
-        }
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int row = l + h * NT;
-#pragma unroll
-      for (int k = 0; k < KG; ++k) sv[h][k] = row < n ? S.r[row * KG + k] : 0.0;
-    }
-    __syncthreads();
     double un[KG], xn[KG];
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
@@ -734,7 +784,7 @@ __device__ int refine_group(const BatchTask& t, RefineLds& S, double anorm, int 
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
       if (k < kn) {
-        const double den = anorm * (anorm * sqrt(xn[k]) + sqrt(rr[k]));
+        const double den = *anorm * (*anorm * sqrt(xn[k]) + sqrt(rr[k]));
         const double be = den > 0.0 ? sqrt(un[k]) / den : 0.0;
         worst = (be > worst || be != be) ? be : worst;
       }
@@ -772,20 +822,9 @@ __device__ int refine_group(const BatchTask& t, RefineLds& S, double anorm, int 
     put_vector(t, sv, S.v);
     __syncthreads();
     double qq[KG] = {};
-    for (int r0 = 0; r0 < m; r0 += NT) {
-      const int i = r0 + l;
-      if (i < m) {
-        double acc[KG] = {};
-        for (int j = 0; j < n; ++j) {
-          const double a = A[(int64_t)j * t.lda + i];
-#pragma unroll
-          for (int k = 0; k < KG; ++k) acc[k] += a * S.v[j * KG + k];
-        }
-#pragma unroll
-        for (int k = 0; k < KG; ++k) qq[k] += acc[k] * acc[k];
-      }
-    }
-    __syncthreads();
+    double none[2][KG];
+    double a2q = 0.0;
+    a_pass<false>(t, k0, kn, S, qq, none, a2q);
     wg_sum<KG>(qq, S.red);
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
@@ -840,8 +879,8 @@ void k_batched_blk(const BatchHeader* table, int queue, int* counter, int* statu
 
 // FP64 refinement of the mixed-precision solves of queues 1 .. 3 (one
 // problem per workgroup, popped from queue counter kBatchQueues).
-__global__ __launch_bounds__(NT) void k_batched_refine(const BatchHeader* table, int* counter,
-                                                       int* status, int* iters) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
+void k_batched_refine(const BatchHeader* table, int* counter, int* status, int* iters) {
   __shared__ __align__(16) RefineLds S;
   int total = 0;
   for (int k = 1; k < kBatchQueues; ++k) total += table->count[k];
@@ -855,18 +894,11 @@ __global__ __launch_bounds__(NT) void k_batched_refine(const BatchHeader* table,
     __syncthreads();
     if (idx >= total) break;
     const BatchTask t = tasks[idx];
-    // ||A||_F
-    double an[1] = {0.0};
-    for (int c = 0; c < t.n; ++c) {
-      const gdouble* ac = gp(t.A) + (int64_t)c * t.lda;
-      for (int i = threadIdx.x; i < t.m; i += NT) an[0] += ac[i] * ac[i];
-    }
-    wg_sum<1>(an, S.red);
-    const double anorm = sqrt(an[0]);
+    double anorm = 0.0;  // ||A||_F, from the first pass over A
     int st = zero_diagonal(t, &S.sing) == INT_MAX ? 0 : kStatusNoConv;
     int most = 0;
     for (int k0 = 0; st == 0 && k0 < t.nrhs; k0 += KG) {
-      const int it = refine_group(t, S, anorm, k0);
+      const int it = refine_group(t, S, &anorm, k0);
       if (it < 0)
         st = kStatusNoConv;
       else
