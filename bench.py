@@ -239,18 +239,22 @@ def bench_config1(torch, miqr, synth, h, reps=20):
 
 def bench_batched(torch, miqr, synth, h, count=10000, seed=4242, precision=None):
     """The serving workload's problems (m in [64, 4096], n in [8, 256], 1-4
-    right-hand sides) solved in one batched call, inputs resident in HBM."""
+    right-hand sides) solved in one batched call, inputs resident in HBM.
+    Mixed precisions: refinement iterations per problem (-1: solved again in
+    FP64); every result meets backward error <= 1e-13."""
+    import numpy as np
     trace = synth.serving_trace(count, 0.0, seed)
     As = [synth.gaussian_device(r.m, r.n, 10 ** 6 + i) for i, r in enumerate(trace)]
     Bs = [synth.gaussian_device(r.m, r.nrhs, 2 * 10 ** 6 + i) for i, r in enumerate(trace)]
     o = h.opts(precision=precision) if precision is not None else None
+    mixed = precision not in (None, miqr.FP64)
     warm = 512
     h.lstsq_batched([a.clone() for a in As[:warm]], [b.clone() for b in Bs[:warm]], o)
     torch.cuda.synchronize()
     h.profile(True)
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    st, _ = h.lstsq_batched(As, Bs, o, want_status=False)
+    res = h.lstsq_batched(As, Bs, o, want_status=False, want_iters=mixed)
     e1.record()
     torch.cuda.synchronize()
     prof = h.profile_totals()
@@ -258,14 +262,36 @@ def bench_batched(torch, miqr, synth, h, count=10000, seed=4242, precision=None)
     ms = e0.elapsed_time(e1)
     flops = sum(nominal_ls_flops(r.m, r.n, r.nrhs) for r in trace)
     kms = sum(v["ms"] for k, v in prof.items() if k.startswith("batched"))
-    return {"problems": count, "shapes": "m~U[64,4096], n~U[8,256] (m>=n), nrhs~U[1,4]",
-            "ms": ms, "solves_per_s": count / (ms * 1e-3), "gflops_nominal": flops / (ms * 1e-3) / 1e9,
-            "kernel_ms": kms, "kernel_tflops": flops / (kms * 1e-3) / 1e12 if kms else None,
-            "kernel_frac_fp64_peak": flops / (kms * 1e-3) / PEAK["fp64"] if kms else None,
-            "kernels": {k: round(v["ms"], 3) for k, v in prof.items()}}
+    out = {"problems": count, "shapes": "m~U[64,4096], n~U[8,256] (m>=n), nrhs~U[1,4]",
+           "ms": ms, "solves_per_s": count / (ms * 1e-3), "gflops_nominal": flops / (ms * 1e-3) / 1e9,
+           "kernel_ms": kms, "kernel_tflops": flops / (kms * 1e-3) / 1e12 if kms else None,
+           "kernel_frac_fp64_peak": flops / (kms * 1e-3) / PEAK["fp64"] if kms else None,
+           "kernels": {k: round(v["ms"], 3) for k, v in prof.items()}}
+    if mixed:
+        its = np.array(res[2])
+        ok = its[its >= 0]
+        out["refinement"] = {"iterations_median": float(np.median(ok)) if ok.size else None,
+                             "iterations_max": int(ok.max()) if ok.size else None,
+                             "fp64_resolves": int((its < 0).sum()),
+                             "backward_error_target": 1e-13}
+    return out
 
 
-def bench_serving(torch, miqr, synth, h, count=10000, seed=99, rates=(0.25, 0.5, 0.9)):
+def bench_batched_all(torch, miqr, synth, h):
+    """bench_batched in FP64 and both mixed precisions on the same problems;
+    speedup = FP64 kernel time / this precision's kernel time."""
+    out = {}
+    for name, p in (("fp64", miqr.FP64), ("mixed_fp32", miqr.MIXED_FP32),
+                    ("mixed_bf16", miqr.MIXED_BF16)):
+        out[name] = bench_batched(torch, miqr, synth, h, precision=p)
+        torch.cuda.empty_cache()
+    for name in ("mixed_fp32", "mixed_bf16"):
+        out[name]["speedup_vs_fp64"] = out["fp64"]["kernel_ms"] / out[name]["kernel_ms"]
+    return out
+
+
+def bench_serving(torch, miqr, synth, h, count=10000, seed=99, rates=(0.25, 0.5, 0.9),
+                  precision=0, followup=True):
     """Open-loop Poisson streams through the serving loop with pinned host
     inputs: capacity first (every request submitted at once), then arrival ->
     completion latency at 25, 50 and 90 % of it; and follow-up right-hand
@@ -290,7 +316,8 @@ def bench_serving(torch, miqr, synth, h, count=10000, seed=99, rates=(0.25, 0.5,
     def run(rate, keep=False):
         trace = synth.serving_trace(count, rate, seed)
         X = [np.zeros((r.n, r.nrhs), order="F") for r in trace]
-        srv = miqr.Server(h, hbm_budget=16 << 30, max_batch=1024, keep_factors=keep)
+        srv = miqr.Server(h, hbm_budget=16 << 30, max_batch=1024, keep_factors=keep,
+                          precision=precision)
         warm = 8
         for i in range(warm):
             srv.submit(*req_views(i, trace[i]), X[i])
@@ -331,6 +358,8 @@ def bench_serving(torch, miqr, synth, h, count=10000, seed=99, rates=(0.25, 0.5,
                              "p50_ms": float(np.percentile(lat, 50) * 1e3),
                              "p99_ms": float(np.percentile(lat, 99) * 1e3),
                              "mean_batch": float(np.mean([d["batch_size"] for d in recs]))})
+    if not followup:
+        return out
     # Follow-up right-hand sides against kept factors: 2000 requests factored
     # with keep_factors, then one more right-hand side each.
     sub = synth.serving_trace(2000, 0.0, seed + 1)
@@ -613,8 +642,11 @@ def main():
         for key, fn in (("tall_skinny", lambda: bench_tall_skinny(torch, miqr, synth, 5)),
                         ("tsqr_1024x64", lambda: bench_config1(torch, miqr, synth, hs[0])),
                         ("mixed_ls", lambda: bench_mixed(torch, miqr, synth, hs[0])),
-                        ("batched", lambda: bench_batched(torch, miqr, synth, hs[0])),
-                        ("serving", lambda: bench_serving(torch, miqr, synth, hs[0]))):
+                        ("batched", lambda: bench_batched_all(torch, miqr, synth, hs[0])),
+                        ("serving", lambda: bench_serving(torch, miqr, synth, hs[0])),
+                        ("serving_mixed_fp32", lambda: bench_serving(
+                            torch, miqr, synth, hs[0], precision=miqr.MIXED_FP32,
+                            followup=False))):
             try:
                 line[key] = fn()
             except Exception as exc:  # reported, never hidden

@@ -277,6 +277,19 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
 #pragma unroll 1
   for (int jj = 0; jj < pw; ++jj) {
     const int qj = rho_q<P>(jj), rj = rho_r<P>(jj);
+    const bool rowj = q == qj;
+    const double rdj = rj == 0 ? rd[0] : (rj == 1 ? rd[1] : (rj == 2 ? rd[2] : rd[3]));
+    // The pivot column to every lane of its row group, and the dot products
+    // with it, do not depend on the reflector: they run alongside the norm,
+    // sqrt and division below.
+    if (cl == jj) {
+#pragma unroll
+      for (int tt = 0; tt < 4; ++tt) *(V*)&F.piv[tt][q][0] = x[tt];
+    }
+    __builtin_amdgcn_wave_barrier();
+    V pv[4];
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) pv[tt] = *(const V*)&F.piv[tt][q][0];
     // Squares of every lane's column; lane jj's sum is the pivot's.
     W s0 = 0, s1 = 0;
 #pragma unroll
@@ -285,45 +298,36 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
       s1 += x[tt][1] * x[tt][1] + x[tt][3] * x[tt][3];
     }
     const double sig2 = readlane(rows_sum((double)s0 + (double)s1), jj);
-    const double rdj = rj == 0 ? rd[0] : (rj == 1 ? rd[1] : (rj == 2 ? rd[2] : rd[3]));
     const double alpha = readlane(rdj, 16 * qj + jj);
-    double tau = 0.0, beta = alpha, sc = 0.0;
-    if (sig2 != 0.0) {
-      const double nrm = sqrt(alpha * alpha + sig2);
-      beta = alpha >= 0.0 ? -nrm : nrm;
-      // tau = (beta - alpha) / beta and sc = 1 / (alpha - beta) from one
-      // division: with d = alpha - beta and g = 1 / (beta d), sc = beta g and
-      // tau = -d^2 g.
-      const double d = alpha - beta;
-      const double g = 1.0 / (beta * d);
-      sc = beta * g;
-      tau = -d * d * g;
-    }
-    if (cl == jj) {
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt) *(V*)&F.piv[tt][q][0] = x[tt];
-    }
-    __builtin_amdgcn_wave_barrier();
     W d0 = 0, d1 = 0;
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) {
-      const V pv = *(const V*)&F.piv[tt][q][0];
-      d0 += pv[0] * x[tt][0] + pv[2] * x[tt][2];
-      d1 += pv[1] * x[tt][1] + pv[3] * x[tt][3];
+      d0 += pv[tt][0] * x[tt][0] + pv[tt][2] * x[tt][2];
+      d1 += pv[tt][1] * x[tt][1] + pv[tt][3] * x[tt][3];
     }
-    // w = R[j, cl] + y_j . x_cl (the R entry enters through its row group).
-    const bool rowj = q == qj;
-    const double z = sc * ((double)d0 + (double)d1) + (rowj ? rdj : 0.0);
-    const double w = rows_sum(z);
+    const double dot = rows_sum((double)d0 + (double)d1);  // x_j . x_cl
+    const double rjc = rows_sum(rowj ? rdj : 0.0);          // R[j, cl] in all four lanes
+    // Reflector (dlarfg rule), without branches: tau = (beta - alpha) / beta
+    // and sc = 1 / (alpha - beta) from one division (d = alpha - beta,
+    // g = 1 / (beta d): sc = beta g, tau = -d^2 g); no reflection when the
+    // column below the diagonal is zero.
+    const double nrm = sqrt(alpha * alpha + sig2);
+    const double bt = alpha >= 0.0 ? -nrm : nrm;
+    const double dd = alpha - bt;
+    const double g = 1.0 / (bt * dd);
+    const bool refl = sig2 != 0.0;
+    const double beta = refl ? bt : alpha;
+    const double sc = refl ? bt * g : 0.0;
+    const double tau = refl ? -dd * dd * g : 0.0;
+    // w = R[j, cl] + y_j . x_cl
+    const double w = rjc + sc * dot;
     if (q == 0 && cl < jj) S.gram[cl][jj] = mysc * w;
     // New R[j, cl]: beta on the diagonal, R[j, cl] - tau w right of it.
     double rnew = rdj;
     if (tau != 0.0 && cl > jj) {
-      // The pivot column is read from LDS again rather than held across
-      // the cross-row sum (register pressure).
       const W f = (W)(tau * w * sc);
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) x[tt] -= f * *(const V*)&F.piv[tt][q][0];
+      for (int tt = 0; tt < 4; ++tt) x[tt] -= f * pv[tt];
       rnew = rdj - tau * w;
     }
     if (cl == jj) {
@@ -356,16 +360,28 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
   // G[k][j] for j > i.  Row i = cl is shared by the four lanes of its column,
   // lane group q holding T[i][rho(q, r)]; each column j is one cross-row sum.
   double tr[4] = {0.0, 0.0, 0.0, 0.0};
+  // The Gram entries and tau of step j + 1 are read from LDS during step j.
+  double gn[4], tn = S.tau[b][0];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) gn[r] = S.gram[rho<P>(q, r)][0];
 #pragma unroll 1
   for (int j = 0; j < pw; ++j) {
+    double gc[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) gc[r] = gn[r];
+    const double tj = tn;
+    if (j + 1 < pw) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) gn[r] = S.gram[rho<P>(q, r)][j + 1];
+      tn = S.tau[b][j + 1];
+    }
     double a = 0.0;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int k = rho<P>(q, r);
-      if (k < j) a += tr[r] * S.gram[k][j];
+      if (k < j) a += tr[r] * gc[r];
     }
     a = rows_sum(a);
-    const double tj = S.tau[b][j];
     const double v = (j == cl) ? tj : ((j > cl) ? -tj * a : 0.0);
     const int qj = rho_q<P>(j), rj = rho_r<P>(j);
     if (q == qj) {
