@@ -423,6 +423,18 @@ def bench_mixed(torch, miqr, synth, h, m=65536, n=2048, conds=(1e2, 1e6)):
     return out
 
 
+# Sub-records of the bench line, in the order they run.
+EXTRAS = {
+    "tall_skinny": lambda torch, miqr, synth, h: bench_tall_skinny(torch, miqr, synth, 5),
+    "tsqr_1024x64": bench_config1,
+    "mixed_ls": bench_mixed,
+    "batched": bench_batched_all,
+    "serving": bench_serving,
+    "serving_mixed_fp32": lambda torch, miqr, synth, h: bench_serving(
+        torch, miqr, synth, h, precision=miqr.MIXED_FP32, followup=False),
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -438,6 +450,8 @@ def main():
                     help="run the step's two factorisations one after the other on one stream")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the sub-records other than the one-stream step")
+    ap.add_argument("--only", choices=sorted(EXTRAS),
+                    help="run one sub-record alone and print it (for profiling)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only; this build has no multi-GPU path "
@@ -502,6 +516,10 @@ def main():
                     t[f] += v[f]
             hs[i].profile(False)
         return tot, per
+
+    if args.only:
+        print(json.dumps({args.only: EXTRAS[args.only](torch, miqr, synth, hs[0])}))
+        return
 
     if args.roofline_pass:
         tot, per = roofline_pass()
@@ -639,16 +657,9 @@ def main():
         line["config"]["gemm_flops_over_nominal"] = blk_fl
         del pristine[:]
         torch.cuda.empty_cache()
-        for key, fn in (("tall_skinny", lambda: bench_tall_skinny(torch, miqr, synth, 5)),
-                        ("tsqr_1024x64", lambda: bench_config1(torch, miqr, synth, hs[0])),
-                        ("mixed_ls", lambda: bench_mixed(torch, miqr, synth, hs[0])),
-                        ("batched", lambda: bench_batched_all(torch, miqr, synth, hs[0])),
-                        ("serving", lambda: bench_serving(torch, miqr, synth, hs[0])),
-                        ("serving_mixed_fp32", lambda: bench_serving(
-                            torch, miqr, synth, hs[0], precision=miqr.MIXED_FP32,
-                            followup=False))):
+        for key, fn in EXTRAS.items():
             try:
-                line[key] = fn()
+                line[key] = fn(torch, miqr, synth, hs[0])
             except Exception as exc:  # reported, never hidden
                 line[key] = {"error": "%s: %s" % (type(exc).__name__, exc)}
             torch.cuda.empty_cache()

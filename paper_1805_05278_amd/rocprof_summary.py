@@ -7,11 +7,17 @@ library's measurements.
         ``*kernel_stats.csv`` under DIR, with the library's kernel names.
 
     python -m paper_1805_05278_amd.rocprof_summary traffic --fetch DIR1 --write DIR2 \
-        --command-fetch CMD1 --command-write CMD2 -o OUT.md --json OUT.json
+        --command-fetch CMD1 --command-write CMD2 --workload NAME -o OUT.md --json OUT.json
         Per-kernel HBM traffic per dispatch from two ``--pmc`` runs (FETCH_SIZE,
         then WRITE_SIZE, both in KiB per dispatch), each scaled by what the same
         counter reads for a plain elementwise copy of 2^27 doubles (1 GiB read,
-        1 GiB written) captured in the same run.
+        1 GiB written) captured in the same run.  The JSON file keeps one record
+        per workload name (other workloads' records are left as they are).
+
+    python -m paper_1805_05278_amd.rocprof_summary counters DIR --command CMD \
+        --workload TEXT -o OUT.md
+        Per-kernel averages of the counters of one ``--pmc`` run (derived
+        counters such as MfmaUtil and VALUBusy as rocprofv3 computes them).
 
 Only reads rocprofv3 output; it runs nothing on the GPU.
 """
@@ -31,6 +37,21 @@ COPY_BYTES = 8.0 * (1 << 27)
 
 # Demangled kernel symbol -> the name the library's event timer uses.
 _PATTERNS = [
+    (r"k_batched_blk<0,", "batched_blk_f64"),
+    (r"k_batched_blk<1,", "batched_blk_fp32"),
+    (r"k_batched_blk<2,", "batched_blk_bf16"),
+    (r"k_batched_refine", "batched_refine"),
+    (r"k_batch_reset", "batched_queue_reset"),
+    (r"k_zero_block_lower", "zero_block_lower"),
+    (r"k_square_last_column", "square_last_column"),
+    (r"k_normalize_r", "normalize_r"),
+    (r"k_find_zero_diag", "find_zero_diag"),
+    (r"k_set_identity", "set_identity"),
+    (r"k_copy_matrix", "copy_matrix"),
+    (r"k_scale_columns", "scale_columns"),
+    (r"k_column_sumsq", "column_sumsq"),
+    (r"k_axpy_cols", "axpy_cols"),
+    (r"k_xpby_cols", "xpby_cols"),
     (r"k_chain_qr<\d+, true, 2>", "tsqr_chain_qr_leaf_rest"),
     (r"k_chain_qr<\d+, true, \d+>", "tsqr_chain_qr_leaf"),
     (r"k_chain_qr_rest<\d+>", "tsqr_chain_qr_leaf_rest"),
@@ -61,6 +82,7 @@ _KERNEL_SOURCES = [
     ("gemm_", ("gemm.hip", "gemm.h", "common.h")),
     ("tsqr_", ("tsqr.hip", "tsqr.h", "common.h")),
     ("batched_ls", ("batched.hip", "batched.h", "common.h")),
+    ("batched_", ("batched_blk.hip", "batched.h", "common.h")),
     ("trsm_diag", ("solve.hip", "solve.h", "common.h")),
 ]
 
@@ -142,7 +164,9 @@ def traffic(args):
     sw = kib / (sum(wr["copy_calibration"]) / len(wr["copy_calibration"]))
     digest = source_digest()
     out = {"_calibration": {"fetch_scale": sf, "write_scale": sw,
-                            "copy_bytes_each_way": COPY_BYTES}}
+                            "copy_bytes_each_way": COPY_BYTES,
+                            "command_fetch": args.command_fetch,
+                            "command_write": args.command_write}}
     lines = ["# HBM traffic per dispatch (rocprofv3 PMC)", "",
              "FETCH_SIZE and WRITE_SIZE (KiB per dispatch, averaged over dispatches) from two",
              "separate counter runs, scaled by the copy calibration: a 2^27-double elementwise",
@@ -162,8 +186,45 @@ def traffic(args):
     lines += ["", "source digest: %s" % digest, ""]
     with open(args.out, "w") as fo:
         fo.write("\n".join(lines))
+    allrec = {}
+    if os.path.exists(args.json):
+        with open(args.json) as fo:
+            allrec = json.load(fo)
+        if "_calibration" in allrec:  # a record without workload keys: replaced
+            allrec = {}
+    allrec[args.workload] = out
     with open(args.json, "w") as fo:
-        json.dump(out, fo, indent=1, sort_keys=True)
+        json.dump(allrec, fo, indent=1, sort_keys=True)
+
+
+def counters(args):
+    per = defaultdict(lambda: defaultdict(list))
+    names = []
+    for r in _rows(_find(args.dir, "counter_collection.csv")):
+        key = library_name(r["Kernel_Name"]) or r["Kernel_Name"][:50]
+        c = r["Counter_Name"]
+        if c not in names:
+            names.append(c)
+        per[key][c].append(float(r["Counter_Value"]))
+    lines = ["# Counters per kernel: %s" % args.workload, "",
+             "Averages per dispatch over the run (derived counters as rocprofv3 computes",
+             "them: MfmaUtil = 100 SQ_VALU_MFMA_BUSY_CYCLES / (GRBM_GUI_ACTIVE x SIMDs);",
+             "VALUBusy = 100 SQ_ACTIVE_INST_VALU / CUs / GRBM_GUI_ACTIVE; MfmaFlopsF64 =",
+             "512 SQ_INSTS_VALU_MFMA_MOPS_F64).", "",
+             "Command (from the repository root on the GPU host):", "", "```", args.command, "```",
+             "", "| kernel | dispatches | " + " | ".join(names) + " |",
+             "|---|---:|" + "---:|" * len(names)]
+    order = sorted(per, key=lambda k: -len(per[k][names[0]]) if names else 0)
+    for k in order:
+        n = max(len(v) for v in per[k].values())
+        cells = []
+        for c in names:
+            v = per[k].get(c, [])
+            cells.append("%.4g" % (sum(v) / len(v)) if v else "")
+        lines.append("| %s | %d | %s |" % (k, n, " | ".join(cells)))
+    lines += ["", "source digest: %s" % source_digest(), ""]
+    with open(args.out, "w") as fo:
+        fo.write("\n".join(lines))
 
 
 def main():
@@ -179,10 +240,16 @@ def main():
     t.add_argument("--write", required=True)
     t.add_argument("--command-fetch", required=True)
     t.add_argument("--command-write", required=True)
+    t.add_argument("--workload", required=True)
     t.add_argument("-o", "--out", required=True)
     t.add_argument("--json", required=True)
+    c = sub.add_parser("counters")
+    c.add_argument("dir")
+    c.add_argument("--command", required=True)
+    c.add_argument("--workload", required=True)
+    c.add_argument("-o", "--out", required=True)
     a = ap.parse_args()
-    {"stats": stats, "traffic": traffic}[a.cmd](a)
+    {"stats": stats, "traffic": traffic, "counters": counters}[a.cmd](a)
 
 
 if __name__ == "__main__":

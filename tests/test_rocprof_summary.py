@@ -68,11 +68,17 @@ def test_traffic_scaled_by_copy(tmp_path):
     class A:
         fetch, write = str(fd), str(wd)
         command_fetch = command_write = "cmd"
+        workload = "w1"
         out = str(tmp_path / "t.md")
         json = str(tmp_path / "t.json")
 
     rs.traffic(A)
-    rec = json.load(open(A.json))
+    # A second workload's record is added beside the first.
+    A.workload = "w2"
+    rs.traffic(A)
+    allrec = json.load(open(A.json))
+    assert sorted(allrec) == ["w1", "w2"]
+    rec = allrec["w1"]
     assert rec["_calibration"]["fetch_scale"] == pytest.approx(2.0)
     assert rec["_calibration"]["write_scale"] == pytest.approx(1.0)
     g = rec["gemm_f64"]
@@ -80,3 +86,24 @@ def test_traffic_scaled_by_copy(tmp_path):
     assert g["hbm_bytes_per_launch"] == pytest.approx((2000.0 * 2.0 + 500.0) * 1024.0)
     assert g["source_digest"] == rs.source_digest("gemm_f64")
     assert os.path.exists(A.out)
+
+
+def test_counters_table(tmp_path):
+    blk = "void miqr::(anonymous namespace)::k_batched_blk<0, 5>(miqr::BatchHeader const*, int, int*, int*)"
+    gemm = "void miqr::k_gemm<128, 128, false, false, 0>(miqr::GemmArgs)"
+    d = tmp_path / "c"
+    d.mkdir()
+    _write_counters(d / "x_counter_collection.csv",
+                    [(gemm, "MfmaUtil", 60.0), (gemm, "MfmaUtil", 40.0), (blk, "MfmaUtil", 10.0),
+                     (gemm, "VALUBusy", 5.0), (blk, "VALUBusy", 30.0)])
+
+    class A:
+        dir = str(d)
+        command = "cmd"
+        workload = "w"
+        out = str(tmp_path / "c.md")
+
+    rs.counters(A)
+    text = open(A.out).read()
+    assert "| gemm_f64 | 2 | 50 | 5 |" in text
+    assert "| batched_blk_f64 | 1 | 10 | 30 |" in text
