@@ -1076,6 +1076,9 @@ miqr_status qr_lstsq_batched_ex(miqr_handle h, void* stream, int64_t count,
     if (iters) iters[i] = itv[(size_t)i];
     if (stv[(size_t)i] != 0 && bad < 0) bad = i;
   }
+  for (int64_t i = 0; i < count; ++i)
+    if (stv[(size_t)i] == kStatusFault)
+      return fail(h, MIQR_EHIP, "item " + std::to_string(i) + ": batched kernel wait bound reached");
   if (bad >= 0)
     return fail(h, MIQR_ESINGULAR, "item " + std::to_string(bad) + ": R(" +
                                        std::to_string(stv[(size_t)bad] - 1) + ") == 0");

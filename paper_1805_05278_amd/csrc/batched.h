@@ -22,6 +22,9 @@ constexpr int kTaskWriteR = 4;  // copy R into A's upper triangle at the end
 // when a mixed-precision solve did not reach its backward-error target (A and
 // B are then left as they were, for an FP64 solve).
 constexpr int kStatusNoConv = -1;
+// A bounded wait inside the batched kernel ran out (a logic error, never
+// expected): the problem's results are not valid.
+constexpr int kStatusFault = -2;
 
 // Queues: tasks are grouped by kernel.  Queue 0 is the column sweep (replays
 // of kept reflectors); queues 1..3 the blocked kernel for problems of at most

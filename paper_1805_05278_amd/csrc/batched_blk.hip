@@ -172,21 +172,54 @@ __device__ __forceinline__ int lane_id() {
   return l;
 }
 
+// LDS buffers for the panels' Y and T: panel p uses buffer p mod NBUF.  With
+// three, panel p + 1 reuses panel p - 2's buffer, whose readers finished
+// before panel p was published, so no factorisation waits for the previous
+// owner's other tiles; with two it waits for the last of panel p - 1's
+// readers.  The FP32 working copies take three; FP64 keeps two, which leaves
+// LDS for three workgroups per CU where its registers allow them (measured
+// faster overall).
 template <typename W>
+struct Bufs {
+  static constexpr int n = sizeof(W) == 8 ? 2 : 3;
+};
+
+template <typename W, int NBUF = Bufs<W>::n>
 struct FactorLds {
-  W ya[2][4][4][16][4];  // Y by accumulator position: [buf][t][q][cl][r] = Y[16 t + rho(q, r)][cl]
-  W yt[2][4][16][4][4];  // Y as the A operand of Y W': [buf][t][i][q][r] = Y[16 t + i][rho(q, r)]
-  W ts[2][16][4][4];     // T: [buf][j][q][r] = T[rho(q, r)][j]
+  W ya[NBUF][4][4][16][4];  // Y by accumulator position: [buf][t][q][cl][r] = Y[16 t + rho(q, r)][cl]
+  W yt[NBUF][4][16][4][4];  // Y as the A operand of Y W': [buf][t][i][q][r] = Y[16 t + i][rho(q, r)]
+  W ts[NBUF][16][4][4];     // T: [buf][j][q][r] = T[rho(q, r)][j]
   W piv[4][4][4];        // the pivot column: [t][q][r]
 };
-template <typename W>
+template <typename W, int NBUF = Bufs<W>::n>
 struct BlkLds {
   FactorLds<W> f;
   double gram[16][17];  // y_i . y_j, i < j, of the current panel
-  double tau[2][16];
+  double tau[NBUF][16];
   double z[2][8];
   int idx, sing;
+  int ready;  // last panel of the block whose Y and T are in LDS
+  int done;   // (wave, panel) pairs whose updates are finished
+  int err;    // a bounded wait ran out (a logic error): the problem fails
 };
+
+// Bounded wait until an LDS counter reaches `target`.  Every wave of the
+// workgroup progresses without the waiting one, so the wait ends; the bound
+// turns a logic error into an error status rather than a hang.
+// Once one wait has run out, every later wait of the problem returns at
+// once, so a fault costs one bound, not one per wait.
+constexpr int kSpinLimit = 1 << 20;
+__device__ __forceinline__ void wait_at_least(int* v, int target, int* err) {
+  if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
+  int spins = 0;
+  while (__hip_atomic_load(v, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
 constexpr int RC = 16;  // rows of A per chunk of a refinement pass
 struct RefineLds {
   double v[kBatchMaxCols * KG];      // a vector of length n per right-hand side, [row][rhs]
@@ -254,7 +287,7 @@ __device__ __forceinline__ void load_tile(const BatchTask& t, int r0, int c,
 // Householder QR of panel p (columns 16 p .. 16 p + pw - 1) of [R; X] by the
 // wave that owns its tile x.  Leaves the reflector tails Y in x's panel
 // columns (the tile's other columns, right-hand sides, are updated), Y and T
-// in LDS buffer p & 1, the diagonal tile of R in global memory, and tau in
+// in LDS buffer p mod NBUF, the diagonal tile of R in global memory, and tau in
 // LDS (and in t.tau for kept factors).
 template <int P>
 __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>::V (&x)[4],
@@ -264,7 +297,8 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
   const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
   const int n = t.n;
   const int pw = min(16, n - 16 * p);
-  const int b = p & 1;
+  constexpr int NBUF = Bufs<W>::n;
+  const int b = p % NBUF;
   const bool keep = (t.flags & kTaskKeep) != 0;
   FactorLds<W>& F = S.f;
   double rd[4];
@@ -402,7 +436,8 @@ __device__ __forceinline__ void update_tile(const BatchTask& t, int p, int c, bo
   using W = typename Prec<P>::W;
   using V = typename Prec<P>::V;
   const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
-  const int b = p & 1;
+  constexpr int NBUF = Bufs<W>::n;
+  const int b = p % NBUF;
   // Y and T are read from LDS for each tile rather than held across the
   // wave's tiles (register pressure): the empty asm keeps the compiler from
   // merging the reads of consecutive tile updates.
@@ -447,8 +482,8 @@ __device__ __forceinline__ void update_tile(const BatchTask& t, int p, int c, bo
 }
 
 // The owner's step for panel pn = p + 1 held in slot `slot`: update by panel
-// p (if any), then factor.  Recursion over the slots keeps every register
-// index a constant.
+// p (if any), then factor and publish.  Recursion over the slots keeps every
+// register index a constant.
 template <int P, int I, int MAXT>
 __device__ __forceinline__ void own_panel(const BatchTask& t, int p, int slot, int bk,
                                           typename Prec<P>::V (&x)[MAXT][4],
@@ -456,7 +491,12 @@ __device__ __forceinline__ void own_panel(const BatchTask& t, int p, int slot, i
   if constexpr (I < MAXT) {
     if (slot == I) {
       if (p >= 0) update_tile<P>(t, p, p + 1, bk == 0, x[I], S.f);
+      // LDS buffer (p + 1) mod NBUF last held panel p + 1 - NBUF: every wave
+      // must be done with it (NW completions per panel up to that one).
+      wait_at_least(&S.done, NW * (p + 2 - Bufs<typename Prec<P>::W>::n), &S.err);
       panel_factor<P>(t, p + 1, bk, x[I], S);
+      if ((threadIdx.x & 63) == 0)
+        __hip_atomic_store(&S.ready, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
       own_panel<P, I + 1, MAXT>(t, p, slot, bk, x, S);
     }
@@ -476,13 +516,26 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
   V x[MAXT][4];
   for (int bk = 0; bk < nblk; ++bk) {
     const bool first = bk == 0;
+    // Every wave has left the previous block's panels (and its waits on the
+    // counters) before they are reset.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      S.ready = -1;
+      S.done = 0;
+    }
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < MAXT; ++i) {
       const int c = w + NW * i;
       if (c < CT) load_tile<P>(t, bk * H, c, x[i]);
     }
+    // Panels are ordered by two LDS counters instead of a barrier per panel:
+    // a wave waits for the panel it applies to be published, and a panel's
+    // owner waits only until its LDS buffer is free.  The next panel's owner
+    // therefore does not wait for this panel's owner to finish its other
+    // tiles.
     for (int p = -1; p < PT; ++p) {
-      if (p >= 0) __syncthreads();  // Y, T of panel p published
+      if (p >= 0) wait_at_least(&S.ready, p, &S.err);  // Y, T of panel p published
       const int pn = p + 1;
       // Look-ahead: the owner of panel pn brings its tile up to date first
       // and factors it.
@@ -493,6 +546,8 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
           const int c = w + NW * i;
           if (c > p && c < CT && (c != pn || pn >= PT)) update_tile<P>(t, p, c, first, x[i], S.f);
         }
+        if ((threadIdx.x & 63) == 0)
+          __hip_atomic_fetch_add(&S.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
     if (keep) {
@@ -513,8 +568,8 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
         }
       }
     }
-    __syncthreads();
   }
+  __syncthreads();
 }
 
 // Sum over the workgroup of KK values per thread; every thread receives the
@@ -883,11 +938,17 @@ void k_batched_blk(const BatchHeader* table, int queue, int* counter, int* statu
     __syncthreads();
     if (idx >= total) break;
     const BatchTask t = tasks[idx];
+    if (threadIdx.x == 0) S.err = 0;
     sweep<P, MAXT>(t, S);
+    const bool err = S.err != 0;
     if constexpr (P == kBlkF64) {
-      const int st = finish_f64(t, S);
+      const int st = err ? kStatusFault : finish_f64(t, S);
       if (st == 0 && (t.flags & kTaskWriteR)) write_r(t);
       if (threadIdx.x == 0) status[t.slot] = st;
+    } else {
+      // The refinement treats a zero diagonal as a failed low-precision
+      // factorisation and leaves the problem to the FP64 pass.
+      if (err && threadIdx.x == 0) gp(t.R)[0] = 0.0;
     }
     __syncthreads();
   }
