@@ -194,7 +194,7 @@ struct FactorLds {
 template <typename W, int NBUF = Bufs<W>::n>
 struct BlkLds {
   FactorLds<W> f;
-  double gram[16][17];  // y_i . y_j, i < j, of the current panel
+  double gram[16][18];  // [k][i] = y_i . y_k, i < k, of the current panel (rows 16-byte aligned)
   double tau[NBUF][16];
   double z[2][8];
   int idx, sing;
@@ -304,6 +304,16 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
   double rd[4];
   load_r<P>(t, p, p, bk == 0, rd);
   double mysc = 0.0;  // scale of this lane's column reflector (y = sc x)
+  // A narrow last panel: the Gram rows and tau of the missing columns are
+  // zero (T's build below reads all sixteen).
+  if (pw < 16) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int k = pw + (lane >> 4) + 4 * r;
+      if (k < 16) S.gram[k][cl] = 0.0;
+    }
+    if (lane < 16 && lane >= pw) S.tau[b][lane] = 0.0;
+  }
   // A loop over the columns (not unrolled: unrolled, the per-column lane
   // masks are loop invariants that the compiler keeps live across the whole
   // sweep).  Row jj of the diagonal R tile sits in register rho_r(jj) of lane
@@ -313,9 +323,8 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
     const int qj = rho_q<P>(jj), rj = rho_r<P>(jj);
     const bool rowj = q == qj;
     const double rdj = rj == 0 ? rd[0] : (rj == 1 ? rd[1] : (rj == 2 ? rd[2] : rd[3]));
-    // The pivot column to every lane of its row group, and the dot products
-    // with it, do not depend on the reflector: they run alongside the norm,
-    // sqrt and division below.
+    // The pivot column to every lane of its row group; the dot products with
+    // it give the pivot's norm and, once the reflector is known, w.
     if (cl == jj) {
 #pragma unroll
       for (int tt = 0; tt < 4; ++tt) *(V*)&F.piv[tt][q][0] = x[tt];
@@ -324,14 +333,6 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
     V pv[4];
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) pv[tt] = *(const V*)&F.piv[tt][q][0];
-    // Squares of every lane's column; lane jj's sum is the pivot's.
-    W s0 = 0, s1 = 0;
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
-      s0 += x[tt][0] * x[tt][0] + x[tt][2] * x[tt][2];
-      s1 += x[tt][1] * x[tt][1] + x[tt][3] * x[tt][3];
-    }
-    const double sig2 = readlane(rows_sum((double)s0 + (double)s1), jj);
     const double alpha = readlane(rdj, 16 * qj + jj);
     W d0 = 0, d1 = 0;
 #pragma unroll
@@ -340,6 +341,8 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
       d1 += pv[tt][1] * x[tt][1] + pv[tt][3] * x[tt][3];
     }
     const double dot = rows_sum((double)d0 + (double)d1);  // x_j . x_cl
+    // Lane jj's dot product is the pivot column's squared norm.
+    const double sig2 = readlane(dot, jj);
     const double rjc = rows_sum(rowj ? rdj : 0.0);          // R[j, cl] in all four lanes
     // Reflector (dlarfg rule), without branches: tau = (beta - alpha) / beta
     // and sc = 1 / (alpha - beta) from one division (d = alpha - beta,
@@ -355,7 +358,7 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
     const double tau = refl ? -dd * dd * g : 0.0;
     // w = R[j, cl] + y_j . x_cl
     const double w = rjc + sc * dot;
-    if (q == 0 && cl < jj) S.gram[cl][jj] = mysc * w;
+    if (q == 0 && cl < jj) S.gram[jj][cl] = mysc * w;
     // New R[j, cl]: beta on the diagonal, R[j, cl] - tau w right of it.
     double rnew = rdj;
     if (tau != 0.0 && cl > jj) {
@@ -390,41 +393,38 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
     for (int r = 0; r < 4; ++r) F.yt[b][tt][rho<P>(q, r)][rho_q<P>(cl)][rho_r<P>(cl)] = y[r];
   }
   __builtin_amdgcn_wave_barrier();
-  // T (Sec. 2.3 recurrence): T[i][i] = tau_i, T[i][j] = -tau_j sum_k T[i][k]
-  // G[k][j] for j > i.  Row i = cl is shared by the four lanes of its column,
-  // lane group q holding T[i][rho(q, r)]; each column j is one cross-row sum.
-  double tr[4] = {0.0, 0.0, 0.0, 0.0};
-  // The Gram entries and tau of step j + 1 are read from LDS during step j.
-  double gn[4], tn = S.tau[b][0];
+  // T of the panel (Sec. 2.3), by columns.  T is the inverse of the upper
+  // triangular S = diag(1 / tau) + striu(V^T V), and V^T V = I + Y^T Y, so
+  // column j of T solves S t = e_j by back-substitution: t_j = tau_j and
+  // t_i = -tau_i sum_{i < k <= j} G[i][k] t_k (G = Y^T Y), a form that also
+  // holds for tau = 0 (zero row and column).  Lane cl computes column cl
+  // alone, with no cross-lane sums; G's entries are broadcast reads of LDS.
+  // acc[i] collects sum_k G[i][k] t_k until row i's turn, then holds t_i.
+  double acc[16];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) gn[r] = S.gram[rho<P>(q, r)][0];
-#pragma unroll 1
-  for (int j = 0; j < pw; ++j) {
-    double gc[4];
+  for (int i = 0; i < 16; ++i) acc[i] = 0.0;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) gc[r] = gn[r];
-    const double tj = tn;
-    if (j + 1 < pw) {
+  for (int k = 15; k >= 0; --k) {
+    // One row of G in registers at a time (the scheduling barrier keeps the
+    // compiler from loading them all up front).
+    __builtin_amdgcn_sched_barrier(0);
+    const double tk = S.tau[b][k];
+    acc[k] = fma(-tk, acc[k], cl == k ? tk : 0.0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) gn[r] = S.gram[rho<P>(q, r)][j + 1];
-      tn = S.tau[b][j + 1];
-    }
-    double a = 0.0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const int k = rho<P>(q, r);
-      if (k < j) a += tr[r] * gc[r];
-    }
-    a = rows_sum(a);
-    const double v = (j == cl) ? tj : ((j > cl) ? -tj * a : 0.0);
-    const int qj = rho_q<P>(j), rj = rho_r<P>(j);
-    if (q == qj) {
-#pragma unroll
-      for (int r = 0; r < 4; ++r) tr[r] = (r == rj) ? v : tr[r];
-    }
+    for (int i = 0; i < k; ++i) acc[i] = fma(S.gram[k][i], acc[k], acc[i]);
   }
+  // ts[j][q][r] = T[rho(q, r)][j]: each lane writes its lane group's four
+  // (every lane stores, so the compiler cannot sink the arithmetic into a
+  // branch behind the loads).
+  V tv;
 #pragma unroll
-  for (int r = 0; r < 4; ++r) F.ts[b][rho<P>(q, r)][rho_q<P>(cl)][rho_r<P>(cl)] = (W)tr[r];
+  for (int r = 0; r < 4; ++r) {
+    double v = acc[rho<P>(0, r)];
+#pragma unroll
+    for (int qq = 1; qq < 4; ++qq) v = q == qq ? acc[rho<P>(qq, r)] : v;
+    tv[r] = (W)v;
+  }
+  *(V*)&F.ts[b][cl][q][0] = tv;
   store_r<P>(t, p, p, rd);
 }
 
