@@ -303,16 +303,16 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
   FactorLds<W>& F = S.f;
   double rd[4];
   load_r<P>(t, p, p, bk == 0, rd);
-  double mysc = 0.0;  // scale of this lane's column reflector (y = sc x)
-  // A narrow last panel: the Gram rows and tau of the missing columns are
-  // zero (T's build below reads all sixteen).
+  double mysc = 0.0;   // scale of this lane's column reflector (y = sc x)
+  double mytau = 0.0;  // and its tau (zero for the missing columns of a narrow panel)
+  // A narrow last panel: the Gram rows of the missing columns are zero (T's
+  // build below reads all sixteen).
   if (pw < 16) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int k = pw + (lane >> 4) + 4 * r;
       if (k < 16) S.gram[k][cl] = 0.0;
     }
-    if (lane < 16 && lane >= pw) S.tau[b][lane] = 0.0;
   }
   // A loop over the columns (not unrolled: unrolled, the per-column lane
   // masks are loop invariants that the compiler keeps live across the whole
@@ -334,9 +334,10 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
 #pragma unroll
     for (int tt = 0; tt < 4; ++tt) pv[tt] = *(const V*)&F.piv[tt][q][0];
     const double alpha = readlane(rdj, 16 * qj + jj);
-    W d0 = 0, d1 = 0;
+    W d0 = pv[0][0] * x[0][0] + pv[0][2] * x[0][2];
+    W d1 = pv[0][1] * x[0][1] + pv[0][3] * x[0][3];
 #pragma unroll
-    for (int tt = 0; tt < 4; ++tt) {
+    for (int tt = 1; tt < 4; ++tt) {
       d0 += pv[tt][0] * x[tt][0] + pv[tt][2] * x[tt][2];
       d1 += pv[tt][1] * x[tt][1] + pv[tt][3] * x[tt][3];
     }
@@ -344,42 +345,46 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
     // Lane jj's dot product is the pivot column's squared norm.
     const double sig2 = readlane(dot, jj);
     const double rjc = rows_sum(rowj ? rdj : 0.0);          // R[j, cl] in all four lanes
-    // Reflector (dlarfg rule), without branches: tau = (beta - alpha) / beta
-    // and sc = 1 / (alpha - beta) from one division (d = alpha - beta,
-    // g = 1 / (beta d): sc = beta g, tau = -d^2 g); no reflection when the
+    // Reflector (dlarfg rule) without branches: with nrm = ||(alpha, x_j)||,
+    // beta = -sign(alpha) nrm, tau = (beta - alpha) / beta = 1 + |alpha| / nrm
+    // and sc = 1 / (alpha - beta); 1 / nrm and sc from the hardware reciprocal
+    // square root and reciprocal with two Newton steps each (a shorter chain
+    // than a correctly rounded sqrt and division).  No reflection when the
     // column below the diagonal is zero.
-    const double nrm = sqrt(alpha * alpha + sig2);
+    const double s2 = fma(alpha, alpha, sig2);
+    double y = __builtin_amdgcn_rsq(s2);
+    y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);
+    y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);
+    const double nrm = s2 * y;
     const double bt = alpha >= 0.0 ? -nrm : nrm;
     const double dd = alpha - bt;
-    const double g = 1.0 / (bt * dd);
+    double z = __builtin_amdgcn_rcp(dd);
+    z = fma(z, fma(-dd, z, 1.0), z);
+    z = fma(z, fma(-dd, z, 1.0), z);
     const bool refl = sig2 != 0.0;
     const double beta = refl ? bt : alpha;
-    const double sc = refl ? bt * g : 0.0;
-    const double tau = refl ? -dd * dd * g : 0.0;
+    const double sc = refl ? z : 0.0;
+    const double tau = refl ? fma(fabs(alpha), y, 1.0) : 0.0;
     // w = R[j, cl] + y_j . x_cl
     const double w = rjc + sc * dot;
     if (q == 0 && cl < jj) S.gram[jj][cl] = mysc * w;
-    // New R[j, cl]: beta on the diagonal, R[j, cl] - tau w right of it.
-    double rnew = rdj;
-    if (tau != 0.0 && cl > jj) {
-      const W f = (W)(tau * w * sc);
+    // Columns right of the pivot: x -= tau w y_j, R[j, cl] -= tau w; the
+    // pivot's lane keeps its reflector and takes beta.
+    const bool right = cl > jj, piv = cl == jj;
+    const double tw = tau * w;
+    const W f = right ? (W)(tw * sc) : (W)0;
 #pragma unroll
-      for (int tt = 0; tt < 4; ++tt) x[tt] -= f * pv[tt];
-      rnew = rdj - tau * w;
-    }
-    if (cl == jj) {
-      mysc = sc;
-      rnew = beta;
-    }
-    if (rowj) {
+    for (int tt = 0; tt < 4; ++tt) x[tt] -= f * pv[tt];
+    const double rnew = piv ? beta : (right ? rdj - tw : rdj);
+    mysc = piv ? sc : mysc;
+    mytau = piv ? tau : mytau;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) rd[r] = (r == rj) ? rnew : rd[r];
-    }
-    if (lane == 0) {
-      S.tau[b][jj] = tau;
-      if (keep) gp(t.tau)[(int64_t)bk * n + 16 * p + jj] = tau;
-    }
+    for (int r = 0; r < 4; ++r) rd[r] = (rowj && r == rj) ? rnew : rd[r];
     __builtin_amdgcn_wave_barrier();
+  }
+  if (lane < 16) {
+    S.tau[b][lane] = mytau;
+    if (keep && lane < pw) gp(t.tau)[(int64_t)bk * n + 16 * p + lane] = mytau;
   }
   // Y in the panel columns; zero for the tile's other columns in the LDS copies.
   const bool acol = cl < pw;
