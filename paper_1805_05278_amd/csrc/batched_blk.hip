@@ -220,10 +220,12 @@ __device__ __forceinline__ void wait_at_least(int* v, int target, int* err) {
     __builtin_amdgcn_s_sleep(1);
   }
 }
-constexpr int RC = 16;  // rows of A per chunk of a refinement pass
+constexpr int RC = 16;       // rows of A per chunk of a refinement pass
+constexpr int RCP = RC + 1;  // padded column stride of the chunk: a thread per column reads
+                             // one row of it without bank conflicts
 struct RefineLds {
   double v[kBatchMaxCols * KG];      // a vector of length n per right-hand side, [row][rhs]
-  double a[kBatchMaxCols * RC];      // the chunk's entries of A, [column][row]
+  double a[kBatchMaxCols * RCP];     // the chunk's entries of A, [column][row]
   double part[NT / RC][RC][KG];      // per-group partial sums of A v, [group][row][rhs]
   double rc[RC][KG];                 // the chunk's residual
   double red[NW][KG];
@@ -753,9 +755,11 @@ __device__ void a_pass(const BatchTask& t, int k0, int kn, RefineLds& S, double 
   const int m = t.m, n = t.n;
   const gdouble* A = gp(t.A);
   const gdouble* B = gp(t.B);
-  // The next chunk's entries are loaded while the current chunk is reduced
-  // (the barriers below order LDS only, so the loads stay in flight).
+  // The next chunk's entries (and its right-hand sides) are loaded while
+  // the current chunk is reduced (the barriers below order LDS only, so the
+  // loads stay in flight).
   double pre[PJ];
+  double bpre = 0.0;
   auto fetch = [&](int r0) {
     // The column group through an empty asm: the 20 column offsets are
     // formed here rather than hoisted out of the loop and held.
@@ -766,6 +770,11 @@ __device__ void a_pass(const BatchTask& t, int k0, int kn, RefineLds& S, double 
     const int64_t step = (int64_t)G * t.lda;
 #pragma unroll
     for (int s = 0; s < PJ; ++s) pre[s] = (i < m && gg + G * s < n) ? ai[s * step] : 0.0;
+    if (RESID && l < RC * KG) {
+      // Row l % RC, right-hand side l / RC of the chunk.
+      const int row = r0 + l % RC, k = l / RC;
+      bpre = (row < m && k < kn) ? B[(int64_t)(k0 + k) * t.ldb + row] : 0.0;
+    }
   };
   fetch(0);
   for (int r0 = 0; r0 < m; r0 += RC) {
@@ -776,7 +785,7 @@ __device__ void a_pass(const BatchTask& t, int k0, int kn, RefineLds& S, double 
       if (j < n) {
         const double a = pre[s];
         if (RESID) {
-          S.a[j * RC + ri] = a;
+          S.a[j * RCP + ri] = a;
           a2 += a * a;
         }
 #pragma unroll
@@ -785,6 +794,7 @@ __device__ void a_pass(const BatchTask& t, int k0, int kn, RefineLds& S, double 
     }
 #pragma unroll
     for (int k = 0; k < KG; ++k) S.part[g][ri][k] = acc[k];
+    const double bv = bpre;
     if (r0 + RC < m) fetch(r0 + RC);
     lds_barrier();
     if (l < RC * KG) {
@@ -795,7 +805,7 @@ __device__ void a_pass(const BatchTask& t, int k0, int kn, RefineLds& S, double 
       for (int gg = 0; gg < G; ++gg) sum += S.part[gg][rr_][k];
       const int row = r0 + rr_;
       double v = sum;
-      if (RESID) v = (row < m && k < kn) ? B[(int64_t)(k0 + k) * t.ldb + row] - sum : 0.0;
+      if (RESID) v = (row < m && k < kn) ? bv - sum : 0.0;
       S.rc[rr_][k] = v;
     }
     lds_barrier();
@@ -810,7 +820,7 @@ __device__ void a_pass(const BatchTask& t, int k0, int kn, RefineLds& S, double 
         if (col < n) {
 #pragma unroll
           for (int q = 0; q < RC; ++q) {
-            const double a = S.a[col * RC + q];
+            const double a = S.a[col * RCP + q];
 #pragma unroll
             for (int k = 0; k < KG; ++k) u[h][k] += a * S.rc[q][k];
           }
@@ -824,7 +834,12 @@ __device__ void a_pass(const BatchTask& t, int k0, int kn, RefineLds& S, double 
 // FP64 refinement of right-hand sides k0 .. k0 + KG - 1 (see the file
 // comment).  Returns the iterations used, or -1 if the target was not met.
 // *anorm: ||A||_F, taken from the first residual pass when zero.
-__device__ int refine_group(const BatchTask& t, RefineLds& S, double* anorm, int k0) {
+// rich: the first iteration is the plain step x += R^-1 R^-T A^T r (one
+// pass over A fewer than a CGLS step; with R from an FP32 factorisation the
+// singular values of A R^-1 are within about u_32 kappa(A) of one, so the
+// step contracts the error by about that much); CGLS from the next
+// iteration on.  Otherwise CGLS throughout.
+__device__ int refine_group(const BatchTask& t, RefineLds& S, double* anorm, int k0, bool rich) {
   const int n = t.n;
   const int kn = min(KG, t.nrhs - k0);
   double xv[2][KG], pv[2][KG], sv[2][KG];
@@ -876,25 +891,37 @@ __device__ int refine_group(const BatchTask& t, RefineLds& S, double* anorm, int
     h3 = h2;
     h2 = h1;
     h1 = worst;
-    // s = R^-T u, p = s + (gamma' / gamma) p
+    // s = R^-T u; CGLS: p = s + (gamma' / gamma) p, t = R^-1 p; the plain
+    // step: t = R^-1 s, x += t.
     fwdsub_t<KG>(t, sv, S.z);
-    double g2[KG];
+    const bool plain = rich && it == 0;
+    if (!plain) {
+      const bool first = it == (rich ? 1 : 0);
+      double g2[KG];
 #pragma unroll
-    for (int k = 0; k < KG; ++k) g2[k] = sv[0][k] * sv[0][k] + sv[1][k] * sv[1][k];
-    wg_sum<KG>(g2, S.red);
+      for (int k = 0; k < KG; ++k) g2[k] = sv[0][k] * sv[0][k] + sv[1][k] * sv[1][k];
+      wg_sum<KG>(g2, S.red);
 #pragma unroll
-    for (int k = 0; k < KG; ++k) {
-      const double be = (it == 0 || gam[k] == 0.0) ? 0.0 : g2[k] / gam[k];
+      for (int k = 0; k < KG; ++k) {
+        const double be = (first || gam[k] == 0.0) ? 0.0 : g2[k] / gam[k];
 #pragma unroll
-      for (int h = 0; h < 2; ++h) pv[h][k] = sv[h][k] + be * (it == 0 ? 0.0 : pv[h][k]);
-      gam[k] = g2[k];
+        for (int h = 0; h < 2; ++h) pv[h][k] = sv[h][k] + be * (first ? 0.0 : pv[h][k]);
+        gam[k] = g2[k];
+      }
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < KG; ++k) sv[h][k] = pv[h][k];
     }
-    // t = R^-1 p (in sv), alpha = gamma / ||A t||^2, x += alpha t
-#pragma unroll
-    for (int h = 0; h < 2; ++h)
-#pragma unroll
-      for (int k = 0; k < KG; ++k) sv[h][k] = pv[h][k];
     backsub<KG>(t, sv, S.z);
+    if (plain) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int k = 0; k < KG; ++k) xv[h][k] += sv[h][k];
+      continue;
+    }
+    // alpha = gamma / ||A t||^2, x += alpha t
     put_vector(t, sv, S.v);
     __syncthreads();
     double qq[KG] = {};
@@ -962,7 +989,7 @@ void k_batched_blk(const BatchHeader* table, int queue, int* counter, int* statu
 // FP64 refinement of the mixed-precision solves of queues 1 .. 3 (one
 // problem per workgroup, popped from queue counter kBatchQueues).
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2)))
-void k_batched_refine(const BatchHeader* table, int* counter, int* status, int* iters) {
+void k_batched_refine(const BatchHeader* table, int* counter, int* status, int* iters, int prec) {
   __shared__ __align__(16) RefineLds S;
   int total = 0;
   for (int k = 1; k < kBatchQueues; ++k) total += table->count[k];
@@ -980,7 +1007,7 @@ void k_batched_refine(const BatchHeader* table, int* counter, int* status, int* 
     int st = zero_diagonal(t, &S.sing) == INT_MAX ? 0 : kStatusNoConv;
     int most = 0;
     for (int k0 = 0; st == 0 && k0 < t.nrhs; k0 += KG) {
-      const int it = refine_group(t, S, &anorm, k0);
+      const int it = refine_group(t, S, &anorm, k0, prec == kBlkF32);
       if (it < 0)
         st = kStatusNoConv;
       else
@@ -1043,7 +1070,8 @@ void batched_blk_launch(hipStream_t s, const BatchHeader* table, int queue, int*
                         int* status, int* iters, int grid, int prec) {
   if (grid <= 0) return;
   if (queue == kBatchQueues) {
-    hipLaunchKernelGGL(k_batched_refine, dim3(grid), dim3(NT), 0, s, table, counter, status, iters);
+    hipLaunchKernelGGL(k_batched_refine, dim3(grid), dim3(NT), 0, s, table, counter, status, iters,
+                       prec);
     return;
   }
   const void* k = blk_kernel(prec, queue);
