@@ -154,6 +154,39 @@ __device__ __forceinline__ double readlane(double v, int lane) {
               (unsigned)__builtin_amdgcn_readlane((int)hi32(v), lane));
 }
 
+// Lane J of each sixteen-lane row to the whole row (DPP row_newbcast).
+template <int J>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __longlong_as_double(
+      __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + J, 0xf, 0xf, false));
+}
+template <int J>
+__device__ __forceinline__ float row_bcast(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xf, 0xf, false));
+}
+
+// Lane group QJ's value to all four groups (lanes cl, cl + 16, cl + 32,
+// cl + 48): v_permlane16_swap leaves rows (0, 0, 2, 2) in one copy and
+// (1, 1, 3, 3) in the other, v_permlane32_swap then halves (0, 1, 0, 1) and
+// (2, 3, 2, 3).
+template <int QJ>
+__device__ __forceinline__ double group_bcast(double v) {
+  unsigned lo = lo32(v), hi = hi32(v);
+  {
+    const auto l = __builtin_amdgcn_permlane16_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane16_swap(hi, hi, false, false);
+    lo = (QJ & 1) ? l[1] : l[0];
+    hi = (QJ & 1) ? h[1] : h[0];
+  }
+  {
+    const auto l = __builtin_amdgcn_permlane32_swap(lo, lo, false, false);
+    const auto h = __builtin_amdgcn_permlane32_swap(hi, hi, false, false);
+    lo = (QJ & 2) ? l[1] : l[0];
+    hi = (QJ & 2) ? h[1] : h[0];
+  }
+  return join(lo, hi);
+}
+
 // The lane index through an empty asm: addresses, masks and row numbers made
 // from it are then computed where they are used.  Otherwise the compiler
 // hoists them out of the sweep's loops as invariants and holds dozens of
@@ -189,7 +222,6 @@ struct FactorLds {
   W ya[NBUF][4][4][16][4];  // Y by accumulator position: [buf][t][q][cl][r] = Y[16 t + rho(q, r)][cl]
   W yt[NBUF][4][16][4][4];  // Y as the A operand of Y W': [buf][t][i][q][r] = Y[16 t + i][rho(q, r)]
   W ts[NBUF][16][4][4];     // T: [buf][j][q][r] = T[rho(q, r)][j]
-  W piv[4][4][4];        // the pivot column: [t][q][r]
 };
 template <typename W, int NBUF = Bufs<W>::n>
 struct BlkLds {
@@ -286,6 +318,88 @@ __device__ __forceinline__ void load_tile(const BatchTask& t, int r0, int c,
     }
 }
 
+// Column JJ of a panel (dlarfg sign rule; norm, beta and tau in FP64) by the
+// wave holding the panel's tile x, with the diagonal R tile in rd (row JJ in
+// register rho_r(JJ) of lane group rho_q(JJ)).  The columns are unrolled, so
+// every register index and lane is a constant: the pivot column reaches the
+// lanes of its row group by DPP broadcasts, R's row JJ reaches all four lane
+// groups by lane permutes.
+template <int P, int JJ>
+__device__ __forceinline__ void column_step(typename Prec<P>::V (&x)[4], double (&rd)[4],
+                                            double& mysc, double& mytau,
+                                            BlkLds<typename Prec<P>::W>& S) {
+  using W = typename Prec<P>::W;
+  using V = typename Prec<P>::V;
+  const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
+  constexpr int qj = rho_q<P>(JJ), rj = rho_r<P>(JJ);
+  const double rdj = rd[rj];
+  V pv[4];
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) pv[tt][r] = row_bcast<JJ>(x[tt][r]);
+  const double alpha = readlane(rdj, 16 * qj + JJ);
+  W d0 = pv[0][0] * x[0][0] + pv[0][2] * x[0][2];
+  W d1 = pv[0][1] * x[0][1] + pv[0][3] * x[0][3];
+#pragma unroll
+  for (int tt = 1; tt < 4; ++tt) {
+    d0 += pv[tt][0] * x[tt][0] + pv[tt][2] * x[tt][2];
+    d1 += pv[tt][1] * x[tt][1] + pv[tt][3] * x[tt][3];
+  }
+  const double dot = rows_sum((double)d0 + (double)d1);  // x_j . x_cl
+  // Lane JJ's dot product is the pivot column's squared norm.
+  const double sig2 = readlane(dot, JJ);
+  const double rjc = group_bcast<qj>(rdj);  // R[j, cl] in all four lanes
+  // Reflector (dlarfg rule) without branches: with nrm = ||(alpha, x_j)||,
+  // beta = -sign(alpha) nrm, tau = (beta - alpha) / beta = 1 + |alpha| / nrm
+  // and sc = 1 / (alpha - beta); 1 / nrm and sc from the hardware reciprocal
+  // square root and reciprocal with two Newton steps each (a shorter chain
+  // than a correctly rounded sqrt and division).  No reflection when the
+  // column below the diagonal is zero.
+  const double s2 = fma(alpha, alpha, sig2);
+  double y = __builtin_amdgcn_rsq(s2);
+  y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);
+  y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);
+  const double nrm = s2 * y;
+  const double bt = alpha >= 0.0 ? -nrm : nrm;
+  const double dd = alpha - bt;
+  double z = __builtin_amdgcn_rcp(dd);
+  z = fma(z, fma(-dd, z, 1.0), z);
+  z = fma(z, fma(-dd, z, 1.0), z);
+  const bool refl = sig2 != 0.0;
+  const double beta = refl ? bt : alpha;
+  const double sc = refl ? z : 0.0;
+  const double tau = refl ? fma(fabs(alpha), y, 1.0) : 0.0;
+  // w = R[j, cl] + y_j . x_cl; for cl < JJ it is the Gram entry y_cl . y_j
+  // once scaled (entries cl >= JJ are written too and never read).
+  const double w = rjc + sc * dot;
+  if (q == 0) S.gram[JJ][cl] = mysc * w;
+  // Columns right of the pivot: x -= tau w y_j, R[j, cl] -= tau w; the
+  // pivot's lane keeps its reflector and takes beta.
+  const bool right = cl > JJ, piv = cl == JJ;
+  const double tw = tau * w;
+  const W f = right ? (W)(tw * sc) : (W)0;
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) x[tt] -= f * pv[tt];
+  const double rnew = piv ? beta : (right ? rdj - tw : rdj);
+  mysc = piv ? sc : mysc;
+  mytau = piv ? tau : mytau;
+  rd[rj] = q == qj ? rnew : rd[rj];
+}
+
+// Columns JJ .. pw - 1 of a panel.
+template <int P, int JJ>
+__device__ __forceinline__ void column_steps(int pw, typename Prec<P>::V (&x)[4], double (&rd)[4],
+                                             double& mysc, double& mytau,
+                                             BlkLds<typename Prec<P>::W>& S) {
+  if constexpr (JJ < 16) {
+    if (JJ < pw) {
+      column_step<P, JJ>(x, rd, mysc, mytau, S);
+      column_steps<P, JJ + 1>(pw, x, rd, mysc, mytau, S);
+    }
+  }
+}
+
 // Householder QR of panel p (columns 16 p .. 16 p + pw - 1) of [R; X] by the
 // wave that owns its tile x.  Leaves the reflector tails Y in x's panel
 // columns (the tile's other columns, right-hand sides, are updated), Y and T
@@ -316,74 +430,7 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
       if (k < 16) S.gram[k][cl] = 0.0;
     }
   }
-  // A loop over the columns (not unrolled: unrolled, the per-column lane
-  // masks are loop invariants that the compiler keeps live across the whole
-  // sweep).  Row jj of the diagonal R tile sits in register rho_r(jj) of lane
-  // group rho_q(jj); registers are picked by selects.
-#pragma unroll 1
-  for (int jj = 0; jj < pw; ++jj) {
-    const int qj = rho_q<P>(jj), rj = rho_r<P>(jj);
-    const bool rowj = q == qj;
-    const double rdj = rj == 0 ? rd[0] : (rj == 1 ? rd[1] : (rj == 2 ? rd[2] : rd[3]));
-    // The pivot column to every lane of its row group; the dot products with
-    // it give the pivot's norm and, once the reflector is known, w.
-    if (cl == jj) {
-#pragma unroll
-      for (int tt = 0; tt < 4; ++tt) *(V*)&F.piv[tt][q][0] = x[tt];
-    }
-    __builtin_amdgcn_wave_barrier();
-    V pv[4];
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) pv[tt] = *(const V*)&F.piv[tt][q][0];
-    const double alpha = readlane(rdj, 16 * qj + jj);
-    W d0 = pv[0][0] * x[0][0] + pv[0][2] * x[0][2];
-    W d1 = pv[0][1] * x[0][1] + pv[0][3] * x[0][3];
-#pragma unroll
-    for (int tt = 1; tt < 4; ++tt) {
-      d0 += pv[tt][0] * x[tt][0] + pv[tt][2] * x[tt][2];
-      d1 += pv[tt][1] * x[tt][1] + pv[tt][3] * x[tt][3];
-    }
-    const double dot = rows_sum((double)d0 + (double)d1);  // x_j . x_cl
-    // Lane jj's dot product is the pivot column's squared norm.
-    const double sig2 = readlane(dot, jj);
-    const double rjc = rows_sum(rowj ? rdj : 0.0);          // R[j, cl] in all four lanes
-    // Reflector (dlarfg rule) without branches: with nrm = ||(alpha, x_j)||,
-    // beta = -sign(alpha) nrm, tau = (beta - alpha) / beta = 1 + |alpha| / nrm
-    // and sc = 1 / (alpha - beta); 1 / nrm and sc from the hardware reciprocal
-    // square root and reciprocal with two Newton steps each (a shorter chain
-    // than a correctly rounded sqrt and division).  No reflection when the
-    // column below the diagonal is zero.
-    const double s2 = fma(alpha, alpha, sig2);
-    double y = __builtin_amdgcn_rsq(s2);
-    y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);
-    y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);
-    const double nrm = s2 * y;
-    const double bt = alpha >= 0.0 ? -nrm : nrm;
-    const double dd = alpha - bt;
-    double z = __builtin_amdgcn_rcp(dd);
-    z = fma(z, fma(-dd, z, 1.0), z);
-    z = fma(z, fma(-dd, z, 1.0), z);
-    const bool refl = sig2 != 0.0;
-    const double beta = refl ? bt : alpha;
-    const double sc = refl ? z : 0.0;
-    const double tau = refl ? fma(fabs(alpha), y, 1.0) : 0.0;
-    // w = R[j, cl] + y_j . x_cl
-    const double w = rjc + sc * dot;
-    if (q == 0 && cl < jj) S.gram[jj][cl] = mysc * w;
-    // Columns right of the pivot: x -= tau w y_j, R[j, cl] -= tau w; the
-    // pivot's lane keeps its reflector and takes beta.
-    const bool right = cl > jj, piv = cl == jj;
-    const double tw = tau * w;
-    const W f = right ? (W)(tw * sc) : (W)0;
-#pragma unroll
-    for (int tt = 0; tt < 4; ++tt) x[tt] -= f * pv[tt];
-    const double rnew = piv ? beta : (right ? rdj - tw : rdj);
-    mysc = piv ? sc : mysc;
-    mytau = piv ? tau : mytau;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) rd[r] = (rowj && r == rj) ? rnew : rd[r];
-    __builtin_amdgcn_wave_barrier();
-  }
+  column_steps<P, 0>(pw, x, rd, mysc, mytau, S);
   if (lane < 16) {
     S.tau[b][lane] = mytau;
     if (keep && lane < pw) gp(t.tau)[(int64_t)bk * n + 16 * p + lane] = mytau;
@@ -488,26 +535,39 @@ __device__ __forceinline__ void update_tile(const BatchTask& t, int p, int c, bo
   }
 }
 
-// The owner's step for panel pn = p + 1 held in slot `slot`: update by panel
-// p (if any), then factor and publish.  Recursion over the slots keeps every
-// register index a constant.
-template <int P, int I, int MAXT>
-__device__ __forceinline__ void own_panel(const BatchTask& t, int p, int slot, int bk,
+// Slot i of a wave's tiles holds the wave's tile (i + rot) mod MAXT (tile
+// w + NW ((i + rot) mod MAXT)): after factoring a panel the owner rotates its
+// slots by one, so the next panel it owns is always in slot 0 and the
+// unrolled factorisation exists once rather than once per slot.
+template <int MAXT>
+__device__ __forceinline__ int slot_tile(int w, int i, int rot) {
+  const int k = i + rot;
+  return w + NW * (k >= MAXT ? k - MAXT : k);
+}
+
+// The owner's step for panel pn = p + 1 (its tile in slot 0): update by
+// panel p (if any), factor, publish, rotate the slots.
+template <int P, int MAXT>
+__device__ __forceinline__ void own_panel(const BatchTask& t, int p, int bk,
                                           typename Prec<P>::V (&x)[MAXT][4],
                                           BlkLds<typename Prec<P>::W>& S) {
-  if constexpr (I < MAXT) {
-    if (slot == I) {
-      if (p >= 0) update_tile<P>(t, p, p + 1, bk == 0, x[I], S.f);
-      // LDS buffer (p + 1) mod NBUF last held panel p + 1 - NBUF: every wave
-      // must be done with it (NW completions per panel up to that one).
-      wait_at_least(&S.done, NW * (p + 2 - Bufs<typename Prec<P>::W>::n), &S.err);
-      panel_factor<P>(t, p + 1, bk, x[I], S);
-      if ((threadIdx.x & 63) == 0)
-        __hip_atomic_store(&S.ready, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-    } else {
-      own_panel<P, I + 1, MAXT>(t, p, slot, bk, x, S);
-    }
-  }
+  using V = typename Prec<P>::V;
+  if (p >= 0) update_tile<P>(t, p, p + 1, bk == 0, x[0], S.f);
+  // LDS buffer (p + 1) mod NBUF last held panel p + 1 - NBUF: every wave
+  // must be done with it (NW completions per panel up to that one).
+  wait_at_least(&S.done, NW * (p + 2 - Bufs<typename Prec<P>::W>::n), &S.err);
+  panel_factor<P>(t, p + 1, bk, x[0], S);
+  if ((threadIdx.x & 63) == 0)
+    __hip_atomic_store(&S.ready, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+  V keep0[4];
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) keep0[tt] = x[0][tt];
+#pragma unroll
+  for (int i = 0; i + 1 < MAXT; ++i)
+#pragma unroll
+    for (int tt = 0; tt < 4; ++tt) x[i][tt] = x[i + 1][tt];
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt) x[MAXT - 1][tt] = keep0[tt];
 }
 
 // The sweep over the row blocks; leaves R and C (the top n rows of Q^T B) in
@@ -536,6 +596,7 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
       const int c = w + NW * i;
       if (c < CT) load_tile<P>(t, bk * H, c, x[i]);
     }
+    int rot = 0;
     // Panels are ordered by two LDS counters instead of a barrier per panel:
     // a wave waits for the panel it applies to be published, and a panel's
     // owner waits only until its LDS buffer is free.  The next panel's owner
@@ -546,11 +607,14 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
       const int pn = p + 1;
       // Look-ahead: the owner of panel pn brings its tile up to date first
       // and factors it.
-      if (pn < PT && w == (pn & 3)) own_panel<P, 0, MAXT>(t, p, pn >> 2, bk, x, S);
+      if (pn < PT && w == (pn & 3)) {
+        own_panel<P, MAXT>(t, p, bk, x, S);
+        ++rot;
+      }
       if (p >= 0) {
 #pragma unroll
         for (int i = 0; i < MAXT; ++i) {
-          const int c = w + NW * i;
+          const int c = slot_tile<MAXT>(w, i, rot);
           if (c > p && c < CT && (c != pn || pn >= PT)) update_tile<P>(t, p, c, first, x[i], S.f);
         }
         if ((threadIdx.x & 63) == 0)
@@ -562,7 +626,7 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
       const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
 #pragma unroll
       for (int i = 0; i < MAXT; ++i) {
-        const int col = 16 * (w + NW * i) + cl;
+        const int col = 16 * slot_tile<MAXT>(w, i, rot) + cl;
         if (col < n) {
           gdouble* dst = gp(t.A + (int64_t)col * t.lda);
 #pragma unroll
