@@ -230,7 +230,8 @@ struct BlkLds {
   double tau[NBUF][16];
   double z[2][8];
   int idx, sing;
-  int ready;  // last panel of the block whose Y and T are in LDS
+  int ready_y;  // last panel of the block whose Y is in LDS
+  int ready;    // last panel of the block whose Y and T are in LDS
   int done;   // (wave, panel) pairs whose updates are finished
   int err;    // a bounded wait ran out (a logic error): the problem fails
 };
@@ -447,6 +448,8 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
     for (int r = 0; r < 4; ++r) F.yt[b][tt][rho<P>(q, r)][rho_q<P>(cl)][rho_r<P>(cl)] = y[r];
   }
   __builtin_amdgcn_wave_barrier();
+  // Y is final: the other waves can form Y^T X while T is built.
+  if (lane == 0) __hip_atomic_store(&S.ready_y, p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   // T of the panel (Sec. 2.3), by columns.  T is the inverse of the upper
   // triangular S = diag(1 / tau) + striu(V^T V), and V^T V = I + Y^T Y, so
   // column j of T solves S t = e_j by back-substitution: t_j = tau_j and
@@ -482,13 +485,15 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
   store_r<P>(t, p, p, rd);
 }
 
-// Update of tile x (column tile c) by panel p.
+// Update of tile x (column tile c) by panel p.  Y of the panel must be
+// published; wait_t: T may not be yet, and is waited for after Y^T X.
 template <int P>
 __device__ __forceinline__ void update_tile(const BatchTask& t, int p, int c, bool first,
                                             typename Prec<P>::V (&x)[4],
-                                            const FactorLds<typename Prec<P>::W>& F) {
+                                            BlkLds<typename Prec<P>::W>& S, bool wait_t) {
   using W = typename Prec<P>::W;
   using V = typename Prec<P>::V;
+  const FactorLds<W>& F = S.f;
   const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
   constexpr int NBUF = Bufs<W>::n;
   const int b = p % NBUF;
@@ -513,6 +518,7 @@ __device__ __forceinline__ void update_tile(const BatchTask& t, int p, int c, bo
   V wv;
 #pragma unroll
   for (int r = 0; r < 4; ++r) wv[r] = (W)(ro[r] + (double)acc[r]);
+  if (wait_t) wait_at_least(&S.ready, p, &S.err);
   const V tv = *(const V*)&F.ts[b][cl][q][0];
   V w2 = {};
 #pragma unroll
@@ -552,7 +558,7 @@ __device__ __forceinline__ void own_panel(const BatchTask& t, int p, int bk,
                                           typename Prec<P>::V (&x)[MAXT][4],
                                           BlkLds<typename Prec<P>::W>& S) {
   using V = typename Prec<P>::V;
-  if (p >= 0) update_tile<P>(t, p, p + 1, bk == 0, x[0], S.f);
+  if (p >= 0) update_tile<P>(t, p, p + 1, bk == 0, x[0], S, true);
   // LDS buffer (p + 1) mod NBUF last held panel p + 1 - NBUF: every wave
   // must be done with it (NW completions per panel up to that one).
   wait_at_least(&S.done, NW * (p + 2 - Bufs<typename Prec<P>::W>::n), &S.err);
@@ -587,6 +593,7 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
     // counters) before they are reset.
     __syncthreads();
     if (threadIdx.x == 0) {
+      S.ready_y = -1;
       S.ready = -1;
       S.done = 0;
     }
@@ -597,13 +604,13 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
       if (c < CT) load_tile<P>(t, bk * H, c, x[i]);
     }
     int rot = 0;
-    // Panels are ordered by two LDS counters instead of a barrier per panel:
-    // a wave waits for the panel it applies to be published, and a panel's
-    // owner waits only until its LDS buffer is free.  The next panel's owner
-    // therefore does not wait for this panel's owner to finish its other
-    // tiles.
+    // Panels are ordered by LDS counters instead of a barrier per panel: a
+    // wave waits for the panel it applies to be published (Y, then T), and a
+    // panel's owner waits only until its LDS buffer is free.  The next
+    // panel's owner therefore does not wait for this panel's owner to finish
+    // its other tiles.
     for (int p = -1; p < PT; ++p) {
-      if (p >= 0) wait_at_least(&S.ready, p, &S.err);  // Y, T of panel p published
+      if (p >= 0) wait_at_least(&S.ready_y, p, &S.err);  // Y of panel p published
       const int pn = p + 1;
       // Look-ahead: the owner of panel pn brings its tile up to date first
       // and factors it.
@@ -612,10 +619,14 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
         ++rot;
       }
       if (p >= 0) {
+        bool wait_t = true;  // the first tile's update waits for T
 #pragma unroll
         for (int i = 0; i < MAXT; ++i) {
           const int c = slot_tile<MAXT>(w, i, rot);
-          if (c > p && c < CT && (c != pn || pn >= PT)) update_tile<P>(t, p, c, first, x[i], S.f);
+          if (c > p && c < CT && (c != pn || pn >= PT)) {
+            update_tile<P>(t, p, c, first, x[i], S, wait_t);
+            wait_t = false;
+          }
         }
         if ((threadIdx.x & 63) == 0)
           __hip_atomic_fetch_add(&S.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
