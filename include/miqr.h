@@ -302,7 +302,8 @@ typedef struct qr_batch_item {
  *   every panel update on FP32 or BF16 MFMA (FP32 accumulation); reflector
  *   generation, T and R stay in FP64.  Each solution is then refined in FP64
  *   against the original A and B (R-preconditioned conjugate gradients on the
- *   normal equations, residual recomputed from A each iteration) until every
+ *   normal equations, residual recomputed from A each iteration; with FP32
+ *   products the first step is x += R^-1 R^-T A^T r) until every
  *   right-hand side's backward error (qr_backward_error's measure) is
  *   <= 1e-13 (the kernel aims at 5e-14, a margin for the rounding of its own
  *   estimate); a problem that does not get there within 40 iterations, or
@@ -313,7 +314,8 @@ typedef struct qr_batch_item {
  *   (that problem's B then holds the top n rows of Q^T B and A is unchanged).
  * Returns MIQR_ESINGULAR if status was given and some problem is singular.
  * Errors: MIQR_EINVAL (a bad item or precision; nothing is enqueued),
- * MIQR_ENOMEM, MIQR_EHIP, MIQR_ENOTSUP. */
+ * MIQR_ENOMEM, MIQR_EHIP (also when a bounded wait inside the kernel ran out,
+ * an internal error: results are then not valid), MIQR_ENOTSUP. */
 miqr_status qr_lstsq_batched(miqr_handle handle, void *stream, int64_t count,
                              const qr_batch_item *items, const qr_opts *opts,
                              int32_t *status);
