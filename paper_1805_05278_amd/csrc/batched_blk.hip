@@ -154,15 +154,17 @@ __device__ __forceinline__ double readlane(double v, int lane) {
               (unsigned)__builtin_amdgcn_readlane((int)hi32(v), lane));
 }
 
-// Lane J of each sixteen-lane row to the whole row (DPP row_newbcast).
+// Lane J of each sixteen-lane row to the whole row (DPP row_newbcast).  The
+// source lane always exists, so bound_ctrl is set: the compiler then needs no
+// "old" value (otherwise it zeroes a register before every move).
 template <int J>
 __device__ __forceinline__ double row_bcast(double v) {
   return __longlong_as_double(
-      __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + J, 0xf, 0xf, false));
+      __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + J, 0xf, 0xf, true));
 }
 template <int J>
 __device__ __forceinline__ float row_bcast(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xf, 0xf, false));
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xf, 0xf, true));
 }
 
 // Lane group QJ's value to all four groups (lanes cl, cl + 16, cl + 32,
@@ -326,12 +328,11 @@ __device__ __forceinline__ void load_tile(const BatchTask& t, int r0, int c,
 // lanes of its row group by DPP broadcasts, R's row JJ reaches all four lane
 // groups by lane permutes.
 template <int P, int JJ>
-__device__ __forceinline__ void column_step(typename Prec<P>::V (&x)[4], double (&rd)[4],
-                                            double& mysc, double& mytau,
+__device__ __forceinline__ void column_step(int q, int cl, typename Prec<P>::V (&x)[4],
+                                            double (&rd)[4], double& mysc, double& mytau,
                                             BlkLds<typename Prec<P>::W>& S) {
   using W = typename Prec<P>::W;
   using V = typename Prec<P>::V;
-  const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
   constexpr int qj = rho_q<P>(JJ), rj = rho_r<P>(JJ);
   const double rdj = rd[rj];
   V pv[4];
@@ -388,15 +389,16 @@ __device__ __forceinline__ void column_step(typename Prec<P>::V (&x)[4], double 
   rd[rj] = q == qj ? rnew : rd[rj];
 }
 
-// Columns JJ .. pw - 1 of a panel.
+// Columns JJ .. pw - 1 of a panel (q, cl: the lane's group and column,
+// formed once per panel).
 template <int P, int JJ>
-__device__ __forceinline__ void column_steps(int pw, typename Prec<P>::V (&x)[4], double (&rd)[4],
-                                             double& mysc, double& mytau,
+__device__ __forceinline__ void column_steps(int pw, int q, int cl, typename Prec<P>::V (&x)[4],
+                                             double (&rd)[4], double& mysc, double& mytau,
                                              BlkLds<typename Prec<P>::W>& S) {
   if constexpr (JJ < 16) {
     if (JJ < pw) {
-      column_step<P, JJ>(x, rd, mysc, mytau, S);
-      column_steps<P, JJ + 1>(pw, x, rd, mysc, mytau, S);
+      column_step<P, JJ>(q, cl, x, rd, mysc, mytau, S);
+      column_steps<P, JJ + 1>(pw, q, cl, x, rd, mysc, mytau, S);
     }
   }
 }
@@ -431,7 +433,7 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
       if (k < 16) S.gram[k][cl] = 0.0;
     }
   }
-  column_steps<P, 0>(pw, x, rd, mysc, mytau, S);
+  column_steps<P, 0>(pw, q, cl, x, rd, mysc, mytau, S);
   if (lane < 16) {
     S.tau[b][lane] = mytau;
     if (keep && lane < pw) gp(t.tau)[(int64_t)bk * n + 16 * p + lane] = mytau;
