@@ -232,8 +232,8 @@ struct BlkLds {
   double tau[NBUF][16];
   double z[2][8];
   int idx, sing;
-  int ready_y;  // last panel of the block whose Y is in LDS
-  int ready;    // last panel of the block whose Y and T are in LDS
+  int ready_y;  // last panel of the block whose Y (the ya copy) is in LDS
+  int ready;    // last panel of the block whose Y (both copies) and T are in LDS
   int done;   // (wave, panel) pairs whose updates are finished
   int err;    // a bounded wait ran out (a logic error): the problem fails
 };
@@ -277,7 +277,9 @@ __device__ __forceinline__ double* r_col(const BatchTask& t, int col) {
 
 // Tile (p, c) of the running R (rows 16 p.., columns 16 c.. of [R | C]) in
 // accumulator order; zero when `zero` (before the first block) and outside
-// n x N.
+// n x N.  The loads are issued unconditionally (an entry outside reads R[0][0]
+// and is replaced by zero): with no branches around them the compiler can
+// count them and need not wait for them before unrelated work.
 template <int P>
 __device__ __forceinline__ void load_r(const BatchTask& t, int p, int c, bool zero, double (&rv)[4]) {
   const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
@@ -287,7 +289,9 @@ __device__ __forceinline__ void load_r(const BatchTask& t, int p, int c, bool ze
 #pragma unroll
   for (int r = 0; r < 4; ++r) {
     const int row = 16 * p + rho<P>(q, r);
-    rv[r] = (in && row < t.n) ? rc[row] : 0.0;
+    const bool ok = in && row < t.n;
+    const double v = rc[ok ? row : 0];
+    rv[r] = ok ? v : 0.0;
   }
 }
 template <int P>
@@ -317,7 +321,9 @@ __device__ __forceinline__ void load_tile(const BatchTask& t, int r0, int c,
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int row = r0 + 16 * tt + rho<P>(q, r);
-      x[tt][r] = (W)((in && row < t.m) ? src[row] : 0.0);
+      const bool ok = in && row < t.m;
+      const double v = src[ok ? row : 0];  // unconditional load (see load_r)
+      x[tt][r] = (W)(ok ? v : 0.0);
     }
 }
 
@@ -410,7 +416,7 @@ __device__ __forceinline__ void column_steps(int pw, int q, int cl, typename Pre
 // LDS (and in t.tau for kept factors).
 template <int P>
 __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>::V (&x)[4],
-                             BlkLds<typename Prec<P>::W>& S) {
+                             double (&rd)[4], BlkLds<typename Prec<P>::W>& S) {
   using W = typename Prec<P>::W;
   using V = typename Prec<P>::V;
   const int lane = lane_id(), q = lane >> 4, cl = lane & 15;
@@ -420,8 +426,6 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
   const int b = p % NBUF;
   const bool keep = (t.flags & kTaskKeep) != 0;
   FactorLds<W>& F = S.f;
-  double rd[4];
-  load_r<P>(t, p, p, bk == 0, rd);
   double mysc = 0.0;   // scale of this lane's column reflector (y = sc x)
   double mytau = 0.0;  // and its tau (zero for the missing columns of a narrow panel)
   // A narrow last panel: the Gram rows of the missing columns are zero (T's
@@ -441,17 +445,21 @@ __device__ void panel_factor(const BatchTask& t, int p, int bk, typename Prec<P>
   // Y in the panel columns; zero for the tile's other columns in the LDS copies.
   const bool acol = cl < pw;
   const W ys = acol ? (W)mysc : (W)0;
+  V yv[4];
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt) {
-    const V y = x[tt] * ys;
-    if (acol) x[tt] = y;
-    *(V*)&F.ya[b][tt][q][cl][0] = y;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) F.yt[b][tt][rho<P>(q, r)][rho_q<P>(cl)][rho_r<P>(cl)] = y[r];
+    yv[tt] = x[tt] * ys;
+    if (acol) x[tt] = yv[tt];
+    *(V*)&F.ya[b][tt][q][cl][0] = yv[tt];
   }
   __builtin_amdgcn_wave_barrier();
-  // Y is final: the other waves can form Y^T X while T is built.
+  // Y is final: the other waves can form Y^T X (which reads the ya copy)
+  // while the yt copy is written and T is built; both are published with T.
   if (lane == 0) __hip_atomic_store(&S.ready_y, p, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+  for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) F.yt[b][tt][rho<P>(q, r)][rho_q<P>(cl)][rho_r<P>(cl)] = yv[tt][r];
   // T of the panel (Sec. 2.3), by columns.  T is the inverse of the upper
   // triangular S = diag(1 / tau) + striu(V^T V), and V^T V = I + Y^T Y, so
   // column j of T solves S t = e_j by back-substitution: t_j = tau_j and
@@ -560,11 +568,15 @@ __device__ __forceinline__ void own_panel(const BatchTask& t, int p, int bk,
                                           typename Prec<P>::V (&x)[MAXT][4],
                                           BlkLds<typename Prec<P>::W>& S) {
   using V = typename Prec<P>::V;
+  // The panel's diagonal R tile, loaded before the update so that its
+  // latency is off the chain (only this wave touches it).
+  double rd[4];
+  load_r<P>(t, p + 1, p + 1, bk == 0, rd);
   if (p >= 0) update_tile<P>(t, p, p + 1, bk == 0, x[0], S, true);
   // LDS buffer (p + 1) mod NBUF last held panel p + 1 - NBUF: every wave
   // must be done with it (NW completions per panel up to that one).
   wait_at_least(&S.done, NW * (p + 2 - Bufs<typename Prec<P>::W>::n), &S.err);
-  panel_factor<P>(t, p + 1, bk, x[0], S);
+  panel_factor<P>(t, p + 1, bk, x[0], rd, S);
   if ((threadIdx.x & 63) == 0)
     __hip_atomic_store(&S.ready, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
   V keep0[4];
