@@ -167,6 +167,105 @@ __device__ __forceinline__ float row_bcast(float v) {
   return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xf, 0xf, true));
 }
 
+// The pivot broadcast fused into the FMAs: v_fmac_{f64,f32}_dpp with
+// row_newbcast:J reads its first source from lane J of the lane's row.  One
+// s_nop 1 at the head of each block gives the two wait states a DPP read
+// needs after a VALU write of its source (the compiler does not look inside
+// the asm); within a block no instruction DPP-reads a register written by
+// the one before it.  xs[4 t + r] is register r of row tile t.
+//   d0 += sum_t (x_J[t][0] x[t][0] + x_J[t][2] x[t][2]), d1 likewise for
+//   registers 1 and 3 (two chains for latency).
+template <int J>
+__device__ __forceinline__ void dots_bcast(const double (&xs)[16], double& d0, double& d1) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %2, %2 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %1, %3, %3 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %0, %4, %4 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %1, %5, %5 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %0, %6, %6 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %1, %7, %7 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %0, %8, %8 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %1, %9, %9 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %0, %10, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %1, %11, %11 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %0, %12, %12 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %1, %13, %13 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %0, %14, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %1, %15, %15 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %0, %16, %16 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %1, %17, %17 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      : "+v"(d0), "+v"(d1)
+      : "v"(xs[0]), "v"(xs[1]), "v"(xs[2]), "v"(xs[3]), "v"(xs[4]), "v"(xs[5]), "v"(xs[6]), "v"(xs[7]), "v"(xs[8]), "v"(xs[9]), "v"(xs[10]), "v"(xs[11]), "v"(xs[12]), "v"(xs[13]), "v"(xs[14]), "v"(xs[15]), "n"(J));
+}
+template <int J>
+__device__ __forceinline__ void dots_bcast(const float (&xs)[16], float& d0, float& d1) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %2, %2 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %3, %3 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %0, %4, %4 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %5, %5 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %0, %6, %6 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %7, %7 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %0, %8, %8 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %9, %9 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %0, %10, %10 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %11, %11 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %0, %12, %12 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %13, %13 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %0, %14, %14 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %15, %15 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %0, %16, %16 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %17, %17 row_newbcast:%18 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      : "+v"(d0), "+v"(d1)
+      : "v"(xs[0]), "v"(xs[1]), "v"(xs[2]), "v"(xs[3]), "v"(xs[4]), "v"(xs[5]), "v"(xs[6]), "v"(xs[7]), "v"(xs[8]), "v"(xs[9]), "v"(xs[10]), "v"(xs[11]), "v"(xs[12]), "v"(xs[13]), "v"(xs[14]), "v"(xs[15]), "n"(J));
+}
+//   x[t][r] += x_J[t][r] nf (lane J's own entries are unchanged when its nf
+//   is zero).
+template <int J>
+__device__ __forceinline__ void update_bcast(double (&xs)[16], double nf) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f64_dpp %0, %0, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %1, %1, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %2, %2, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %3, %3, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %4, %4, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %5, %5, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %6, %6, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %7, %7, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %8, %8, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %9, %9, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %10, %10, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %11, %11, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %12, %12, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %13, %13, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %14, %14, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f64_dpp %15, %15, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      : "+v"(xs[0]), "+v"(xs[1]), "+v"(xs[2]), "+v"(xs[3]), "+v"(xs[4]), "+v"(xs[5]), "+v"(xs[6]), "+v"(xs[7]), "+v"(xs[8]), "+v"(xs[9]), "+v"(xs[10]), "+v"(xs[11]), "+v"(xs[12]), "+v"(xs[13]), "+v"(xs[14]), "+v"(xs[15])
+      : "v"(nf), "n"(J));
+}
+template <int J>
+__device__ __forceinline__ void update_bcast(float (&xs)[16], float nf) {
+  asm("s_nop 1\n\t"
+      "v_fmac_f32_dpp %0, %0, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %1, %1, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %2, %2, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %3, %3, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %4, %4, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %5, %5, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %6, %6, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %7, %7, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %8, %8, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %9, %9, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %10, %10, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %11, %11, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %12, %12, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %13, %13, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %14, %14, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      "v_fmac_f32_dpp %15, %15, %16 row_newbcast:%17 row_mask:0xf bank_mask:0xf bound_ctrl:1\n\t"
+      : "+v"(xs[0]), "+v"(xs[1]), "+v"(xs[2]), "+v"(xs[3]), "+v"(xs[4]), "+v"(xs[5]), "+v"(xs[6]), "+v"(xs[7]), "+v"(xs[8]), "+v"(xs[9]), "+v"(xs[10]), "+v"(xs[11]), "+v"(xs[12]), "+v"(xs[13]), "+v"(xs[14]), "+v"(xs[15])
+      : "v"(nf), "n"(J));
+}
+
 // Lane group QJ's value to all four groups (lanes cl, cl + 16, cl + 32,
 // cl + 48): v_permlane16_swap leaves rows (0, 0, 2, 2) in one copy and
 // (1, 1, 3, 3) in the other, v_permlane32_swap then halves (0, 1, 0, 1) and
@@ -341,19 +440,14 @@ __device__ __forceinline__ void column_step(int q, int cl, typename Prec<P>::V (
   using V = typename Prec<P>::V;
   constexpr int qj = rho_q<P>(JJ), rj = rho_r<P>(JJ);
   const double rdj = rd[rj];
-  V pv[4];
+  W xs[16];
 #pragma unroll
   for (int tt = 0; tt < 4; ++tt)
 #pragma unroll
-    for (int r = 0; r < 4; ++r) pv[tt][r] = row_bcast<JJ>(x[tt][r]);
+    for (int r = 0; r < 4; ++r) xs[4 * tt + r] = x[tt][r];
   const double alpha = readlane(rdj, 16 * qj + JJ);
-  W d0 = pv[0][0] * x[0][0] + pv[0][2] * x[0][2];
-  W d1 = pv[0][1] * x[0][1] + pv[0][3] * x[0][3];
-#pragma unroll
-  for (int tt = 1; tt < 4; ++tt) {
-    d0 += pv[tt][0] * x[tt][0] + pv[tt][2] * x[tt][2];
-    d1 += pv[tt][1] * x[tt][1] + pv[tt][3] * x[tt][3];
-  }
+  W d0 = 0, d1 = 0;
+  dots_bcast<JJ>(xs, d0, d1);
   const double dot = rows_sum((double)d0 + (double)d1);  // x_j . x_cl
   // Lane JJ's dot product is the pivot column's squared norm.
   const double sig2 = readlane(dot, JJ);
@@ -386,9 +480,12 @@ __device__ __forceinline__ void column_step(int q, int cl, typename Prec<P>::V (
   // pivot's lane keeps its reflector and takes beta.
   const bool right = cl > JJ, piv = cl == JJ;
   const double tw = tau * w;
-  const W f = right ? (W)(tw * sc) : (W)0;
+  const W nf = right ? (W)(-(tw * sc)) : (W)0;
+  update_bcast<JJ>(xs, nf);
 #pragma unroll
-  for (int tt = 0; tt < 4; ++tt) x[tt] -= f * pv[tt];
+  for (int tt = 0; tt < 4; ++tt)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) x[tt][r] = xs[4 * tt + r];
   const double rnew = piv ? beta : (right ? rdj - tw : rdj);
   mysc = piv ? sc : mysc;
   mytau = piv ? tau : mytau;
@@ -595,7 +692,7 @@ __device__ __forceinline__ void own_panel(const BatchTask& t, int p, int bk,
 template <int P, int MAXT>
 __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
   using V = typename Prec<P>::V;
-  const int w = threadIdx.x >> 6;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // in a scalar register
   const int n = t.n, N = n + t.nrhs;
   const int CT = (N + 15) >> 4, PT = (n + 15) >> 4;
   const int nblk = (t.m + H - 1) / H;
