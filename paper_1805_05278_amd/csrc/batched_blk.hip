@@ -154,19 +154,6 @@ __device__ __forceinline__ double readlane(double v, int lane) {
               (unsigned)__builtin_amdgcn_readlane((int)hi32(v), lane));
 }
 
-// Lane J of each sixteen-lane row to the whole row (DPP row_newbcast).  The
-// source lane always exists, so bound_ctrl is set: the compiler then needs no
-// "old" value (otherwise it zeroes a register before every move).
-template <int J>
-__device__ __forceinline__ double row_bcast(double v) {
-  return __longlong_as_double(
-      __builtin_amdgcn_update_dpp(0ll, __double_as_longlong(v), 0x150 + J, 0xf, 0xf, true));
-}
-template <int J>
-__device__ __forceinline__ float row_bcast(float v) {
-  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x150 + J, 0xf, 0xf, true));
-}
-
 // The pivot broadcast fused into the FMAs: v_fmac_{f64,f32}_dpp with
 // row_newbcast:J reads its first source from lane J of the lane's row.  One
 // s_nop 1 at the head of each block gives the two wait states a DPP read
@@ -429,9 +416,9 @@ __device__ __forceinline__ void load_tile(const BatchTask& t, int r0, int c,
 // Column JJ of a panel (dlarfg sign rule; norm, beta and tau in FP64) by the
 // wave holding the panel's tile x, with the diagonal R tile in rd (row JJ in
 // register rho_r(JJ) of lane group rho_q(JJ)).  The columns are unrolled, so
-// every register index and lane is a constant: the pivot column reaches the
-// lanes of its row group by DPP broadcasts, R's row JJ reaches all four lane
-// groups by lane permutes.
+// every register index and lane is a constant: the pivot column enters the
+// dot products and the update through DPP broadcasts inside the FMAs, R's
+// row JJ reaches all four lane groups by lane permutes.
 template <int P, int JJ>
 __device__ __forceinline__ void column_step(int q, int cl, typename Prec<P>::V (&x)[4],
                                             double (&rd)[4], double& mysc, double& mytau,
