@@ -320,7 +320,7 @@ struct BlkLds {
   int idx, sing;
   int ready_y;  // last panel of the block whose Y (the ya copy) is in LDS
   int ready;    // last panel of the block whose Y (both copies) and T are in LDS
-  int done;   // (wave, panel) pairs whose updates are finished
+  int done[NW];  // per wave: panels of the block whose updates it has finished
   int err;    // a bounded wait ran out (a logic error): the problem fails
 };
 
@@ -337,6 +337,24 @@ __device__ __forceinline__ void wait_at_least(int* v, int target, int* err) {
     if (++spins > kSpinLimit) {
       __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       break;
+    }
+    __builtin_amdgcn_s_sleep(1);
+  }
+}
+// Bounded wait until every wave's counter v[w] reaches `target` (same bound
+// and error rule as wait_at_least).
+__device__ __forceinline__ void wait_all_at_least(int* v, int target, int* err) {
+  if (__hip_atomic_load(err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)) return;
+  int spins = 0;
+  for (;;) {
+    int lo = __hip_atomic_load(&v[0], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+#pragma unroll
+    for (int w = 1; w < NW; ++w)
+      lo = min(lo, __hip_atomic_load(&v[w], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+    if (lo >= target) return;
+    if (++spins > kSpinLimit) {
+      __hip_atomic_store(err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      return;
     }
     __builtin_amdgcn_s_sleep(1);
   }
@@ -658,8 +676,9 @@ __device__ __forceinline__ void own_panel(const BatchTask& t, int p, int bk,
   load_r<P>(t, p + 1, p + 1, bk == 0, rd);
   if (p >= 0) update_tile<P>(t, p, p + 1, bk == 0, x[0], S, true);
   // LDS buffer (p + 1) mod NBUF last held panel p + 1 - NBUF: every wave
-  // must be done with it (NW completions per panel up to that one).
-  wait_at_least(&S.done, NW * (p + 2 - Bufs<typename Prec<P>::W>::n), &S.err);
+  // must be done with it (a per-wave count: a total could be reached while
+  // one slow wave still reads the buffer).
+  wait_all_at_least(S.done, p + 2 - Bufs<typename Prec<P>::W>::n, &S.err);
   panel_factor<P>(t, p + 1, bk, x[0], rd, S);
   if ((threadIdx.x & 63) == 0)
     __hip_atomic_store(&S.ready, p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
@@ -693,7 +712,8 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
     if (threadIdx.x == 0) {
       S.ready_y = -1;
       S.ready = -1;
-      S.done = 0;
+#pragma unroll
+      for (int k = 0; k < NW; ++k) S.done[k] = 0;
     }
     __syncthreads();
 #pragma unroll
@@ -727,7 +747,7 @@ __device__ void sweep(const BatchTask& t, BlkLds<typename Prec<P>::W>& S) {
           }
         }
         if ((threadIdx.x & 63) == 0)
-          __hip_atomic_fetch_add(&S.done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+          __hip_atomic_store(&S.done[w], p + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }
     if (keep) {
