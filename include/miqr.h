@@ -265,9 +265,13 @@ miqr_status qr_solve_r(miqr_handle handle, void *stream, int64_t n,
  * result of this library is gated on (the paper defines none):
  *   beta_j = ||A^T r_j||_2 / (||A||_F (||A||_F ||x_j||_2 + ||r_j||_2)),
  *   r_j = B[:, j] - A X[:, j],
- * zero exactly at a least-squares solution, computed in FP64 on the device.
+ * zero exactly at a least-squares solution, computed in FP64 on the device
+ * (the norms' quotients are taken before any product, so no product of norms
+ * overflows).
  *   A (m x n, lda >= m), B (m x nrhs, ldb >= m), X (n x nrhs, ldx >= n):
- *   device, read only.  beta (host, nrhs doubles) receives the values.
+ *   device, read only.  beta (host, nrhs doubles) receives the values, NaN
+ *   where a norm's sum of squares overflows (entries of 1e154 and beyond);
+ *   the mixed-precision solvers never accept such a value as converged.
  * Synchronises the stream.  Uses the handle's workspace.
  * Errors: MIQR_EINVAL (sizes, NULL pointers), MIQR_ENOMEM, MIQR_EHIP. */
 miqr_status qr_backward_error(miqr_handle handle, void *stream, int64_t m, int64_t n,

@@ -182,6 +182,21 @@ miqr_status do_factor(miqr_handle h, hipStream_t s, const Tuning& tune, const Fa
   return factor_with(h, s, tune, w, a);
 }
 
+// beta from the norms fa = ||A||_F, un = ||A^T r||, xn = ||x||, rn = ||r||,
+// with the quotients taken before any product, so that no product of norms
+// overflows: (un / fa / fa) / (xn + rn / fa).  NaN when a norm is not finite
+// (a sum of squares overflowed: the estimate cannot decide, and callers treat
+// it as not converged); 0 for x = 0 and r = 0.
+double backward_from_norms(double fa, double un, double xn, double rn) {
+  if (!(std::isfinite(fa) && std::isfinite(un) && std::isfinite(xn) && std::isfinite(rn)))
+    return NAN;
+  if (fa == 0.0) return un == 0.0 ? 0.0 : NAN;
+  const double den = xn + rn / fa;
+  return den > 0.0 ? (un / fa / fa) / den : 0.0;
+}
+// The larger of two estimates; a NaN one wins (std::max would drop it).
+double worse_of(double w, double be) { return (be > w || be != be) ? be : w; }
+
 // beta(x)_c = ||A^T r_c|| / (||A||_F (||A||_F ||x_c|| + ||r_c||)),
 // r = b - A x, all FP64 on the device (A0, B0 originals; X solutions).  Rr
 // (m x k) and U (n x k) are scratch, nrm 3k + n doubles.  Writes every
@@ -216,10 +231,9 @@ double backward_error_dev(hipStream_t s, int64_t m, int64_t n, int64_t k, const 
   double worst = 0.0;
   for (int64_t c = 0; c < k; ++c) {
     const double rn = std::sqrt(hn[c]), gn = std::sqrt(hn[k + c]), xn = std::sqrt(hn[2 * k + c]);
-    const double den = fa * (fa * xn + rn);
-    const double be = den > 0 ? gn / den : 0.0;
+    const double be = backward_from_norms(fa, gn, xn, rn);
     if (out) out[c] = be;
-    worst = std::max(worst, be);
+    worst = worse_of(worst, be);
   }
   return worst;
 }
@@ -391,8 +405,7 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
       for (int64_t c = 0; c < k; ++c) {
         const double un = std::sqrt(hn[k + c]), xn = std::sqrt(hn[2 * k + c]),
                      rn = std::sqrt(hn[3 * k + c]);
-        const double den = fa * (fa * xn + rn);
-        worst = std::max(worst, den > 0 ? un / den : 0.0);
+        worst = worse_of(worst, backward_from_norms(fa, un, xn, rn));
       }
     };
     for (int64_t c = 0; c < k; ++c) gam[c] = hn[c];
@@ -401,7 +414,8 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
     std::vector<double> hist{worst};
     auto settled = [&]() { return worst <= tol && (worst <= floor || worst > 0.5 * prev); };
     bool done = worst <= floor;
-    while (!done && iters < maxit && e == hipSuccess) {
+    // A NaN estimate (overflowing norms) cannot improve: fall back at once.
+    while (!done && worst == worst && iters < maxit && e == hipSuccess) {
       ++iters;
       // t = R^{-1} p, q = A t, alpha = gamma / ||q||^2
       G('N', n, k, n, 1.0, w.Rinv, n, MASK_UPPER, w.P, n, 0.0, w.Tv, n);
@@ -428,7 +442,7 @@ miqr_status lstsq_mixed(miqr_handle h, hipStream_t s, int64_t m, int64_t n, int6
       fetch_norms(4 * k);
       prev = worst;
       backward();
-      if (settled()) break;
+      if (settled() || worst != worst) break;
       // Give up early (and fall back) when the contraction over the last five
       // iterations cannot reach the gate within the iteration cap.
       hist.push_back(worst);

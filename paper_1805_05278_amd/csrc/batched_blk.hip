@@ -457,26 +457,14 @@ __device__ __forceinline__ void column_step(int q, int cl, typename Prec<P>::V (
   // Lane JJ's dot product is the pivot column's squared norm.
   const double sig2 = readlane(dot, JJ);
   const double rjc = group_bcast<qj>(rdj);  // R[j, cl] in all four lanes
-  // Reflector (dlarfg rule) without branches: with nrm = ||(alpha, x_j)||,
-  // beta = -sign(alpha) nrm, tau = (beta - alpha) / beta = 1 + |alpha| / nrm
-  // and sc = 1 / (alpha - beta); 1 / nrm and sc from the hardware reciprocal
-  // square root and reciprocal with two Newton steps each (a shorter chain
-  // than a correctly rounded sqrt and division).  No reflection when the
-  // column below the diagonal is zero.
-  const double s2 = fma(alpha, alpha, sig2);
-  double y = __builtin_amdgcn_rsq(s2);
-  y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);
-  y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);
-  const double nrm = s2 * y;
-  const double bt = alpha >= 0.0 ? -nrm : nrm;
-  const double dd = alpha - bt;
-  double z = __builtin_amdgcn_rcp(dd);
-  z = fma(z, fma(-dd, z, 1.0), z);
-  z = fma(z, fma(-dd, z, 1.0), z);
+  // Reflector (dlarfg rule) without branches; no reflection when the column
+  // below the diagonal is zero.
+  double bt, tr, z;
+  reflector(alpha, sig2, bt, tr, z);
   const bool refl = sig2 != 0.0;
   const double beta = refl ? bt : alpha;
   const double sc = refl ? z : 0.0;
-  const double tau = refl ? fma(fabs(alpha), y, 1.0) : 0.0;
+  const double tau = refl ? tr : 0.0;
   // w = R[j, cl] + y_j . x_cl; for cl < JJ it is the Gram entry y_cl . y_j
   // once scaled (entries cl >= JJ are written too and never read).
   const double w = rjc + sc * dot;
@@ -1064,12 +1052,24 @@ __device__ int refine_group(const BatchTask& t, RefineLds& S, double* anorm, int
     wg_sum<KG>(rr, S.red);
     wg_sum<KG>(un, S.red);
     wg_sum<KG>(xn, S.red);
+    // beta with the quotients taken before any product (no product of norms
+    // overflows); a non-finite norm (an overflowed sum of squares) gives NaN,
+    // which never counts as converged and ends the refinement.
     double worst = 0.0;
+    const double an = *anorm;
 #pragma unroll
     for (int k = 0; k < KG; ++k) {
       if (k < kn) {
-        const double den = *anorm * (*anorm * sqrt(xn[k]) + sqrt(rr[k]));
-        const double be = den > 0.0 ? sqrt(un[k]) / den : 0.0;
+        const double un_ = sqrt(un[k]), xn_ = sqrt(xn[k]), rn_ = sqrt(rr[k]);
+        double be;
+        if (!(isfinite(an) && isfinite(un_) && isfinite(xn_) && isfinite(rn_)))
+          be = NAN;
+        else if (an == 0.0)
+          be = un_ == 0.0 ? 0.0 : NAN;
+        else {
+          const double den = xn_ + rn_ / an;
+          be = den > 0.0 ? (un_ / an / an) / den : 0.0;
+        }
         worst = (be > worst || be != be) ? be : worst;
       }
     }

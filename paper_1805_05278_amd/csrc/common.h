@@ -57,6 +57,33 @@ __device__ __forceinline__ double oct_sum(double v) {
   return v;
 }
 
+// Householder reflector of a column (alpha; x) with ||x||^2 = ss > 0 (the
+// dlarfg sign rule): beta = -sign(alpha) ||(alpha; x)||,
+// tau = (beta - alpha) / beta = 1 + |alpha| / ||(alpha; x)|| and
+// scale = 1 / (alpha - beta), the factor that turns x into the reflector's
+// tail.  1 / ||.|| and 1 / (alpha - beta) come from the hardware reciprocal
+// square root and reciprocal with two Newton steps each: within a few ulps of
+// the correctly rounded values, on a much shorter dependent chain than a
+// correctly rounded sqrt and division.  The hardware reciprocal square root
+// is accurate to about 2^-26 over the whole range, subnormal inputs included
+// (measured on gfx950), and every intermediate stays in range
+// (|alpha - beta| >= ||.|| >= 2^-538), so no scaling is needed.
+__device__ __forceinline__ void reflector(double alpha, double ss, double& beta, double& tau,
+                                          double& scale) {
+  const double s2 = fma(alpha, alpha, ss);
+  double y = __builtin_amdgcn_rsq(s2);
+  y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);
+  y = fma(0.5 * y, fma(-(s2 * y), y, 1.0), y);  // 1 / ||(alpha; x)||
+  const double nrm = s2 * y;
+  beta = alpha >= 0.0 ? -nrm : nrm;
+  const double dd = alpha - beta;
+  double z = __builtin_amdgcn_rcp(dd);
+  z = fma(z, fma(-dd, z, 1.0), z);
+  z = fma(z, fma(-dd, z, 1.0), z);
+  scale = z;
+  tau = fma(fabs(alpha), y, 1.0);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o);

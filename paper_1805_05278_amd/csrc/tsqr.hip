@@ -135,12 +135,7 @@ __device__ __forceinline__ void qr_step(double (&x)[Lay<H>::CPT][8], int nbr,
         const double ss = group_sum<RG>((s4[0] + s4[1]) + (s4[2] + s4[3]));
         const double alpha = first ? group_sum<RG>(av) : Rs[j][j];
         double beta = alpha, tau = 0.0, scale = 1.0;
-        if (ss != 0.0) {
-          const double nrm = sqrt(alpha * alpha + ss);
-          beta = (alpha >= 0.0) ? -nrm : nrm;
-          tau = (beta - alpha) / beta;
-          scale = 1.0 / (alpha - beta);
-        }
+        if (ss != 0.0) reflector(alpha, ss, beta, tau, scale);
         double nv[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
@@ -705,18 +700,7 @@ __device__ void mfma_block_qr(const TileCoord& tc, double (&xt)[8][4], int nbr,
         const double ss = half_wave_sum((s4[0] + s4[1]) + (s4[2] + s4[3]));
         const double alpha = first ? half_wave_sum(av) : Rs[jg][jg];
         double beta = alpha, tau = 0.0, scale = 1.0;
-        if (ss != 0.0) {
-          const double nrm = sqrt(alpha * alpha + ss);
-          beta = (alpha >= 0.0) ? -nrm : nrm;
-          // One division for both scalars (two would be serialised on VCC):
-          // with r = 1 / (beta (alpha - beta)), 1 / (alpha - beta) = beta r and
-          // (beta - alpha) / beta = -(alpha - beta)^2 r.  |alpha - beta| is
-          // between nrm and 2 nrm, so the product has the range of alpha^2 + ss.
-          const double amb = alpha - beta;
-          const double r = 1.0 / (beta * amb);
-          scale = beta * r;
-          tau = -(amb * amb) * r;
-        }
+        if (ss != 0.0) reflector(alpha, ss, beta, tau, scale);
         double nv[8];
 #pragma unroll
         for (int s = 0; s < 8; ++s) {
