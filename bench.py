@@ -221,19 +221,35 @@ def bench_config1(torch, miqr, synth, h, reps=20):
     Q = miqr.colmajor(1024, 64)
     sign = torch.empty(64, dtype=torch.float64, device="cuda")
     o = h.opts(leaf_rows=128, chain=1, arity=2, normalize=True, sign_out=sign, Q=Q)
-    times = []
-    for r in range(reps + 3):
-        A.copy_(A0)
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        h.factor(A, T, o)
-        e1.record()
-        torch.cuda.synchronize()
-        if r >= 3:
-            times.append(e0.elapsed_time(e1) * 1e3)
-    times.sort()
+
+    def timed():
+        times, walls = [], []
+        for r in range(reps + 3):
+            A.copy_(A0)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            e0.record()
+            h.factor(A, T, o)
+            e1.record()
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            if r >= 3:
+                times.append(e0.elapsed_time(e1) * 1e3)
+                walls.append((t1 - t0) * 1e6)
+        times.sort()
+        walls.sort()
+        return times, walls
+
+    times, walls = timed()
+    # The same calls replayed from one captured launch graph.
+    h.graphs(True)
+    gtimes, gwalls = timed()
+    h.graphs(False)
     return {"us_median": times[len(times) // 2], "us_min": times[0],
+            "us_median_wall": walls[len(walls) // 2],
+            "graph_us_median": gtimes[len(gtimes) // 2], "graph_us_min": gtimes[0],
+            "graph_us_median_wall": gwalls[len(gwalls) // 2],
             "config": "1024x64, 8 blocks of 128 rows, binary tree, R diag >= 0, thin Q"}
 
 

@@ -174,6 +174,25 @@ miqr_status miqr_profile_get(miqr_handle handle, int index, char *name,
                              int name_len, double *ms, int64_t *launches,
                              double *bytes, double *flops);
 
+/* Launch graphs for qr_factor.  While enabled (enable != 0), qr_factor
+ * records its launch sequence (the kernels of Alg. 2, its TSQR base cases of
+ * Sec. 6.1 and the look-ahead stream's share, with their order) into a HIP
+ * graph the first time it sees a key, and replays that graph as one launch on
+ * the caller's stream on every later call with the same key.  The key is the
+ * shape, the leading dimensions, the addresses of A, T, Q and sign_out, every
+ * option and the handle's workspace address; a call with any of them
+ * different is captured anew.  Replays run the same kernels in the same
+ * order: results are bitwise those of the eager calls.  The buffers must stay
+ * allocated while their graph may still be replayed (re-using an address for
+ * a new buffer of the same shape is fine: the graph reads whatever is there
+ * when it runs).  At most 64 graphs are kept per handle (all are dropped when
+ * a 65th is captured, and when the workspace grows).  While per-kernel timing
+ * (miqr_profile_enable) is on, calls run eagerly.  Disabling synchronises the
+ * device and drops every graph.  miqr_graph_count returns the number kept.
+ * Other entry points always launch eagerly. */
+miqr_status miqr_graphs_enable(miqr_handle handle, int enable);
+int64_t miqr_graph_count(miqr_handle handle);
+
 /* QR factorisation in place (Alg. 2 with the TSQR base case of Sec. 6.1).
  *   A  (m x n, lda >= m, m >= n >= 1): on return R in the upper triangle and
  *      V's strict lower trapezoid below it.

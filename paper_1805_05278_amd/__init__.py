@@ -140,6 +140,10 @@ def lib():
         L.miqr_last_gemm_flops.restype = ctypes.c_double
         L.miqr_profile_enable.argtypes = [_vp, ctypes.c_int]
         L.miqr_profile_enable.restype = st
+        L.miqr_graphs_enable.argtypes = [_vp, ctypes.c_int]
+        L.miqr_graphs_enable.restype = st
+        L.miqr_graph_count.argtypes = [_vp]
+        L.miqr_graph_count.restype = _i64
         L.miqr_profile_kernels.argtypes = [_vp]
         L.miqr_profile_kernels.restype = ctypes.c_int
         L.miqr_profile_get.argtypes = [_vp, ctypes.c_int, ctypes.c_char_p, ctypes.c_int,
@@ -225,6 +229,15 @@ class Handle:
     def profile(self, enable: bool = True):
         """Start (clearing earlier totals) or stop per-kernel event timing."""
         self._check(lib().miqr_profile_enable(self._h, 1 if enable else 0))
+
+    def graphs(self, enable: bool = True):
+        """Replay factor() calls as captured launch graphs (off: eager, and
+        every kept graph dropped)."""
+        self._check(lib().miqr_graphs_enable(self._h, 1 if enable else 0))
+
+    def graph_count(self) -> int:
+        """Number of factorisation graphs the handle keeps."""
+        return lib().miqr_graph_count(self._h)
 
     def profile_totals(self) -> dict:
         """{kernel: dict(ms, launches, bytes, flops)} accumulated while enabled."""

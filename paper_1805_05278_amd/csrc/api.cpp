@@ -51,6 +51,13 @@ miqr_status hip_fail(miqr_handle h, hipError_t e, const char* where) {
   return fail(h, MIQR_EHIP, std::string(where) + ": " + hipGetErrorString(e));
 }
 
+// Drop every captured factorisation graph (their launches name workspace
+// addresses that are about to change, or the handle is going away).
+void clear_graphs(miqr_handle h) {
+  for (auto& kv : h->graph_cache) hipGraphExecDestroy(kv.second.exec);
+  h->graph_cache.clear();
+}
+
 miqr_status ensure_ws(miqr_handle h, size_t bytes) {
   if (bytes <= h->ws_bytes) return MIQR_OK;
   hipError_t e = hipSetDevice(h->device);
@@ -58,6 +65,7 @@ miqr_status ensure_ws(miqr_handle h, size_t bytes) {
   if (h->ws) {
     e = hipDeviceSynchronize();
     if (e != hipSuccess) return hip_fail(h, e, "hipDeviceSynchronize");
+    clear_graphs(h);
     hipFree(h->ws);
     h->ws = nullptr;
     h->ws_bytes = 0;
@@ -85,6 +93,9 @@ struct Arena {
 };
 
 bool bad_ptr(const void* p) { return p == nullptr; }
+
+// Captured factorisation graphs kept per handle (all dropped when full).
+constexpr size_t kMaxGraphs = 64;
 
 // Validation of the tuning and output options shared by the entry points
 // (h may be null: the message is then dropped).
@@ -173,12 +184,66 @@ miqr_status factor_with(miqr_handle h, hipStream_t s, const Tuning& tune, const 
   return MIQR_OK;
 }
 
-// Factor in the handle's workspace (grown to the layout first).
-miqr_status do_factor(miqr_handle h, hipStream_t s, const Tuning& tune, const FactorArgs& a) {
+// The factorisation as one graph launch on s: the launch sequence of this
+// key is captured once (on the handle's capture stream, whose work is only
+// recorded, never run), instantiated and kept; later calls with the same key
+// replay it.  The same kernels in the same order give bitwise the same
+// results as the eager launches.
+miqr_status factor_graph(miqr_handle h, hipStream_t s, const Tuning& tune, const FactorWs& w,
+                         const FactorArgs& a, int prec) {
+  GraphKey k{a.m, a.n, a.lda, a.ldt, a.Q ? a.ldq : 0, a.A, a.T, a.Q, a.sign, h->ws,
+             a.normalize, prec, tune.b, tune.bstar, tune.nb, tune.leaf_rows, tune.chain,
+             tune.arity, tune.t_layout, tune.lookahead};
+  auto it = h->graph_cache.find(k);
+  if (it == h->graph_cache.end()) {
+    hipError_t e = hipSuccess;
+    if (!h->cap) e = hipStreamCreateWithFlags(&h->cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(h, e, "capture stream");
+    if (tune.t_layout == T_BLOCKED && tune.lookahead) {
+      Lookahead la;  // created before the capture starts
+      miqr_status st = ensure_lookahead(h, &la);
+      if (st != MIQR_OK) return st;
+    }
+    e = hipStreamBeginCapture(h->cap, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
+    const miqr_status st = factor_with(h, h->cap, tune, w, a);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(h->cap, &g);
+    if (st != MIQR_OK || e != hipSuccess) {
+      if (g) hipGraphDestroy(g);
+      (void)hipGetLastError();
+      return st != MIQR_OK ? st : hip_fail(h, e, "hipStreamEndCapture");
+    }
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    hipGraphDestroy(g);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGraphInstantiate");
+    if (h->graph_cache.size() >= kMaxGraphs) {
+      e = hipDeviceSynchronize();  // no dropped graph may still be running
+      if (e != hipSuccess) {
+        hipGraphExecDestroy(x);
+        return hip_fail(h, e, "hipDeviceSynchronize");
+      }
+      clear_graphs(h);
+    }
+    it = h->graph_cache.emplace(k, GraphEntry{x, h->gemm_flops}).first;
+  }
+  const hipError_t e = hipGraphLaunch(it->second.exec, s);
+  if (e != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
+  h->gemm_flops = it->second.gemm_flops;
+  return MIQR_OK;
+}
+
+// Factor in the handle's workspace (grown to the layout first); through a
+// captured graph when the handle has graphs on (and per-kernel timing off:
+// its events and host reads cannot be captured).
+miqr_status do_factor(miqr_handle h, hipStream_t s, const Tuning& tune, const FactorArgs& a,
+                      int prec = MIQR_FP64) {
   const FactorLayout L = factor_layout(a.m, a.n, tune, a.Q != nullptr);
   miqr_status st = ensure_ws(h, (size_t)L.total * sizeof(double));
   if (st != MIQR_OK) return st;
   const FactorWs w = carve_factor((double*)h->ws, L);
+  if (h->graphs && !h->profiling) return factor_graph(h, s, tune, w, a, prec);
   return factor_with(h, s, tune, w, a);
 }
 
@@ -561,6 +626,8 @@ miqr_status miqr_destroy(miqr_handle h) {
   if (!h) return MIQR_EINVAL;
   hipSetDevice(h->device);
   hipDeviceSynchronize();
+  clear_graphs(h);
+  if (h->cap) hipStreamDestroy(h->cap);
   if (h->ws) hipFree(h->ws);
   if (h->dflag) hipFree(h->dflag);
   if (h->pin_tasks) hipHostFree(h->pin_tasks);
@@ -623,6 +690,19 @@ miqr_status miqr_profile_enable(miqr_handle h, int enable) {
   return MIQR_OK;
 }
 
+miqr_status miqr_graphs_enable(miqr_handle h, int enable) {
+  if (!h) return MIQR_EINVAL;
+  if (!enable && !h->graph_cache.empty()) {
+    hipSetDevice(h->device);
+    hipDeviceSynchronize();
+    clear_graphs(h);
+  }
+  h->graphs = enable != 0;
+  return MIQR_OK;
+}
+
+int64_t miqr_graph_count(miqr_handle h) { return h ? (int64_t)h->graph_cache.size() : 0; }
+
 int miqr_profile_kernels(miqr_handle h) {
   if (!h) return 0;
   h->timer.collect();
@@ -677,7 +757,7 @@ miqr_status qr_factor(miqr_handle h, void* stream, int64_t m, int64_t n, double*
     a.normalize = o->normalize;
     a.sign = o->sign_out;
   }
-  return do_factor(h, (hipStream_t)stream, tune, a);
+  return do_factor(h, (hipStream_t)stream, tune, a, prec);
 }
 
 miqr_status qr_factor_noalloc(miqr_handle h, void* stream, int64_t m, int64_t n, double* A,

@@ -24,6 +24,26 @@ struct TuneKey {
   }
 };
 
+// Key of the handle's factorisation graphs: everything a captured launch
+// sequence bakes in (shape, leading dimensions, buffer addresses, options and
+// the resolved tuning).
+struct GraphKey {
+  int64_t m, n, lda, ldt, ldq;
+  const void *A, *T, *Q, *sign, *ws;
+  int64_t normalize, prec, b, bstar, nb, leaf_rows, chain, arity, layout, lookahead;
+  bool operator<(const GraphKey& o) const {
+    return std::tie(m, n, lda, ldt, ldq, A, T, Q, sign, ws, normalize, prec, b, bstar, nb,
+                    leaf_rows, chain, arity, layout, lookahead) <
+           std::tie(o.m, o.n, o.lda, o.ldt, o.ldq, o.A, o.T, o.Q, o.sign, o.ws, o.normalize,
+                    o.prec, o.b, o.bstar, o.nb, o.leaf_rows, o.chain, o.arity, o.layout,
+                    o.lookahead);
+  }
+};
+struct GraphEntry {
+  hipGraphExec_t exec = nullptr;
+  double gemm_flops = 0.0;
+};
+
 struct miqr_ctx {
   int device = 0;
   char* ws = nullptr;
@@ -46,4 +66,9 @@ struct miqr_ctx {
   hipEvent_t ev_panel = nullptr;
   hipEvent_t ev_update = nullptr;
   std::map<TuneKey, miqr::Tuning> tune_cache;
+  // qr_factor launch sequences captured once and replayed (miqr_graphs_enable);
+  // cap is the stream they are captured on (never executed on).
+  bool graphs = false;
+  hipStream_t cap = nullptr;
+  std::map<GraphKey, GraphEntry> graph_cache;
 };
