@@ -460,6 +460,9 @@ def main():
     ap.add_argument("--no-profile", action="store_true", help="no roofline pass")
     ap.add_argument("--roofline-pass", action="store_true",
                     help="run only the one-stream, no-look-ahead pass with kernel events")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="the roofline pass's two factorisations without the per-kernel "
+                         "event timer (for rocprofv3 counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (PMC byte-counter scale)")
     ap.add_argument("--serial", action="store_true",
@@ -535,6 +538,18 @@ def main():
 
     if args.only:
         print(json.dumps({args.only: EXTRAS[args.only](torch, miqr, synth, hs[0])}))
+        return
+
+    if args.pmc_pass:
+        # One factorisation of each matrix (counter collection serialises
+        # every dispatch, so a repeat would double a long run).
+        nola = [hs[i].opts(t_layout=miqr.T_BLOCKED, lookahead=False) for i in range(2)]
+        As = fresh()
+        torch.cuda.synchronize()
+        for i in range(2):
+            hs[i].factor(As[i], Ts[i], nola[i])
+            torch.cuda.synchronize()
+            print(json.dumps({"pmc_pass_done": list(SHAPES[i])}), flush=True)
         return
 
     if args.roofline_pass:
