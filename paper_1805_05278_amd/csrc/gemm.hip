@@ -39,6 +39,32 @@ struct GemmArgs {
   int add_identity;
 };
 
+// Tile of this workgroup.  Workgroups are dealt to the 8 XCDs in turn (id
+// mod 8), and each XCD has its own L2; the linear id is remapped so that XCD
+// k runs a contiguous range of the tile order.  The order walks groups of
+// kGroup row tiles across all column tiles (column by column inside a group),
+// split by split: the workgroups an XCD runs together share a few row panels
+// of the left operand and column panels of the right one (or one split-K
+// slice of V) in its L2, instead of every XCD fetching every panel.  Any
+// bijection gives the same results: only the placement of the tiles changes.
+struct TileId {
+  int64_t x, y, z;
+  __device__ TileId() {
+    constexpr int64_t kXcd = 8, kGroup = 8;
+    const int64_t gx = gridDim.x, gy = gridDim.y;
+    const int64_t nb = gx * gy * gridDim.z;
+    const int64_t id = blockIdx.x + gx * (blockIdx.y + gy * (int64_t)blockIdx.z);
+    const int64_t q = nb / kXcd, r = nb % kXcd, k = id % kXcd, j = id / kXcd;
+    const int64_t lid = k * q + min(k, r) + j;
+    const int64_t per = gx * gy, t = lid % per;
+    z = lid / per;
+    const int64_t g = t / (kGroup * gy), x0 = g * kGroup, gs = min(gx - x0, kGroup);
+    const int64_t u = t - g * kGroup * gy;
+    x = x0 + u % gs;
+    y = u / gs;
+  }
+};
+
 template <int CMP>
 struct MfmaTraits;
 
@@ -207,8 +233,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   __shared__ T Bs[2][BK][BN + PAD];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
   const int wm = w & 1, wn = w >> 1;
-  const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
-  const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+  const TileId tid;
+  const int64_t i0 = tid.x * BM, j0 = tid.y * BN;
+  const int64_t kbeg = tid.z * g.kchunk;
   const int64_t kend = min(g.K, kbeg + g.kchunk);
   const int nslab = (int)((kend - kbeg + BK - 1) / BK);
 
@@ -323,7 +350,8 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
-        cv[b][r] = (row_ok && j < g.N && !g.P && g.beta != 0.0) ? g.C[i + j * g.ldc] : 0.0;
+        cv[b][r] = (row_ok && j < g.N && !g.P && g.beta != 0.0)
+                       ? g.C[i + j * g.ldc] : 0.0;
       }
   };
   load_c(0);
@@ -347,7 +375,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
         if (!row_ok || j >= g.N) continue;
-        if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = out[b][r];
+        if (g.P) g.P[tid.z * g.M * g.N + i + j * g.M] = out[b][r];
         else g.C[i + j * g.ldc] = out[b][r];
       }
   }
@@ -371,8 +399,9 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
   __shared__ __align__(16) __bf16 Bs[2][BN][KP];
   const int t = threadIdx.x, w = t >> 6, l = t & 63, li = l & 15, lk = l >> 4;
   const int wm = w & 1, wn = w >> 1;
-  const int64_t i0 = (int64_t)blockIdx.x * BM, j0 = (int64_t)blockIdx.y * BN;
-  const int64_t kbeg = (int64_t)blockIdx.z * g.kchunk;
+  const TileId tid;
+  const int64_t i0 = tid.x * BM, j0 = tid.y * BN;
+  const int64_t kbeg = tid.z * g.kchunk;
   const int64_t kend = min(g.K, kbeg + g.kchunk);
   const int nslab = (int)((kend - kbeg + BK - 1) / BK);
   f4 acc[SA][SB];
@@ -468,7 +497,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int64_t j = j0 + wn * WN + 16 * b + 4 * lk + r;
-        cv[b][r] = (row_ok && j < g.N && !g.P && g.beta != 0.0) ? g.C[i + j * g.ldc] : 0.0;
+        cv[b][r] = (row_ok && j < g.N && !g.P && g.beta != 0.0)
+                       ? g.C[i + j * g.ldc] : 0.0;
       }
   };
   load_c(0);
@@ -492,7 +522,7 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int64_t j = j0 + wn * WN + 16 * b + 4 * lk + r;
         if (!row_ok || j >= g.N) continue;
-        if (g.P) g.P[(int64_t)blockIdx.z * g.M * g.N + i + j * g.M] = out[b][r];
+        if (g.P) g.P[tid.z * g.M * g.N + i + j * g.M] = out[b][r];
         else g.C[i + j * g.ldc] = out[b][r];
       }
   }
