@@ -239,36 +239,13 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const int64_t kend = min(g.K, kbeg + g.kchunk);
   const int nslab = (int)((kend - kbeg + BK - 1) / BK);
 
-  // FP64: the accumulators start from (beta / alpha) C, so that the result
-  // alpha acc = beta C + alpha op(A) op(B) needs no C read after the K loop;
-  // the C loads are issued here, beside the first slab's, and their latency
-  // overlaps it.  (FP32 accumulators would round C; split-K partials add C
-  // once, in the reduction.)
-  const bool cinit = CMP == COMPUTE_F64 && !g.P && g.beta != 0.0 && g.alpha != 0.0;
   Acc acc[SA][SB];
-  if (cinit) {
-    const double cs = g.beta / g.alpha, id = g.add_identity ? 1.0 / g.alpha : 0.0;
 #pragma unroll
-    for (int a = 0; a < SA; ++a) {
-      const int64_t i = i0 + wm * WM + 16 * a + li;
+  for (int a = 0; a < SA; ++a)
 #pragma unroll
-      for (int b = 0; b < SB; ++b)
+    for (int b = 0; b < SB; ++b)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
-          // clamped into the matrix and masked after the load
-          const double c = g.C[min(i, g.M - 1) + min(j, g.N - 1) * g.ldc];
-          acc[a][b][r] = (i < g.M && j < g.N) ? cs * c + (i == j ? id : 0.0) : 0.0;
-        }
-    }
-  } else {
-#pragma unroll
-    for (int a = 0; a < SA; ++a)
-#pragma unroll
-      for (int b = 0; b < SB; ++b)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
-  }
+      for (int r = 0; r < 4; ++r) acc[a][b][r] = 0;
 
   LA_t la;
   LB_t lb;
@@ -377,7 +354,7 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
                        ? g.C[i + j * g.ldc] : 0.0;
       }
   };
-  if (!cinit) load_c(0);
+  load_c(0);
 #pragma unroll
   for (int a = 0; a < SA; ++a) {
     const int64_t i = i0 + wm * WM + 16 * a + li;
@@ -389,10 +366,9 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
       for (int r = 0; r < 4; ++r) {
         const int64_t j = j0 + wn * WN + 16 * b + Tr::row(lk, r);
         const double v = g.alpha * (double)acc[a][b][r];
-        out[b][r] = (g.P || cinit) ? v
-                                   : v + g.beta * cv[b][r] + ((g.add_identity && i == j) ? 1.0 : 0.0);
+        out[b][r] = g.P ? v : v + g.beta * cv[b][r] + ((g.add_identity && i == j) ? 1.0 : 0.0);
       }
-    if (!cinit && a + 1 < SA) load_c(a + 1);
+    if (a + 1 < SA) load_c(a + 1);
 #pragma unroll
     for (int b = 0; b < SB; ++b)
 #pragma unroll
