@@ -243,6 +243,7 @@ hipError_t factor_blocked(hipStream_t s, const Lookahead& la, const Tuning& t, c
     return wy_update(st, m - j, wd, nc, A + j + j * lda, lda, a.T + j * a.ldt, a.ldt, 'T',
                      A + j + c1 * lda, lda, W1, W2, sc, scn, a.update_compute, flops);
   };
+  constexpr int64_t kAuxChunk = 3072;  // columns per look-ahead update launch group
   const bool ahead = t.lookahead && la.aux && la.ev_panel && la.ev_update;
   hipError_t e = factor_panel(0);
   for (int64_t j = 0; j < n && e == hipSuccess; j += nb) {
@@ -255,8 +256,14 @@ hipError_t factor_blocked(hipStream_t s, const Lookahead& la, const Tuning& t, c
       // is factored; panel k + 1 is updated and factored here meanwhile.
       e = hipEventRecord(la.ev_panel, s);
       if (e == hipSuccess) e = hipStreamWaitEvent(la.aux, la.ev_panel, 0);
-      if (e == hipSuccess)
-        e = update(la.aux, j, c2, n, w.ua1, w.ua2, w.ua_cap, w.scratch_aux, w.scratch_aux_n);
+      // In column chunks: a blocked TSQR workgroup needs a CU with no GEMM
+      // workgroup on it, and the end of each chunk's launches drains CUs for
+      // the panel kernels waiting on the main stream (3072 columns measured
+      // best: 16384^2 alone 245 -> 233 ms; 2048 and 4096 in between, 1024
+      // slower than no chunks).
+      for (int64_t cc = c2; cc < n && e == hipSuccess; cc += kAuxChunk)
+        e = update(la.aux, j, cc, std::min<int64_t>(n, cc + kAuxChunk), w.ua1, w.ua2, w.ua_cap,
+                   w.scratch_aux, w.scratch_aux_n);
       if (e == hipSuccess) e = hipEventRecord(la.ev_update, la.aux);
       if (e == hipSuccess) e = update(s, j, c1, c2, w.u1, w.u2, w.u_cap, w.scratch, w.scratch_n);
       if (e == hipSuccess) e = factor_panel(c1);

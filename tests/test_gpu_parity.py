@@ -335,6 +335,30 @@ def test_blocked_matches_oracle(miqr, m, n, nb, lookahead):
     check_blocked(A, g, nb)
 
 
+def test_blocked_lookahead_column_chunks(miqr):
+    """More than 3072 trailing columns: the look-ahead stream updates them in
+    column chunks (early panels here take two)."""
+    m_, h = miqr
+    A = synth.gaussian(3400, 3300, 611)
+    g = gpu_factor_blocked(m_, h, A, 64, lookahead=True)
+    check_blocked(A, g, 64)
+
+
+def test_blocked_lookahead_equals_one_stream_8192(miqr):
+    """8192^2 with nb = 128 (up to three update chunks per panel): the
+    look-ahead factors equal the one-stream ones to rounding (the one-stream
+    path is checked against the oracle above).  A skipped or doubled chunk
+    would change whole columns by O(1)."""
+    m_, h = miqr
+    A = synth.gaussian(8192, 8192, 612)
+    ga = gpu_factor_blocked(m_, h, A, 128, lookahead=True)
+    g1 = gpu_factor_blocked(m_, h, A, 128, lookahead=False)
+    # normwise, at the size where kappa(A) ~ 1e4 amplifies rounding in V and T
+    assert rel(ga["R"], g1["R"]) <= 1e-11
+    assert rel(ga["V"], g1["V"]) <= 1e-10
+    assert rel(ga["Tb"], g1["Tb"]) <= 1e-10
+
+
 @pytest.mark.parametrize("b,bstar", [(128, 64), (128, 32), (32, 32)])
 def test_blocked_with_thresholds(miqr, b, bstar):
     m_, h = miqr
